@@ -1,0 +1,237 @@
+"""FP64 CPU oracle for ALTO MTTKRP and the CP-ALS sweep -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does; it shares
+no code with this package (see ``alto_oracle.c`` for the per-nonzero loops).
+
+The per-nonzero loops (encode, decode, order, partition, MTTKRP) are plain C
+in ``alto_oracle.c``; the CP-ALS sweep is composed here in NumPy FP64 from
+those loops and library primitives (matrix products, Cholesky, symmetric
+eigendecomposition), step by step as Algorithm "alg:cp-als" of the paper
+(arXiv 2403.06348, Sec. "CP-ALS") lists them.
+
+Parity is pinned (in ``tests/test_oracle_*.py``) against: the paper's worked
+example (Fig. "format-comparison"(a), Sec. "ALTO Tensor Generation" and
+"Workload Partitioning and Scheduling"), Eq. 1-3, dense-unfolding brute
+force, the rank-1 closed form, single-nonzero and all-ones special cases,
+the cross-mode invariant, a NumPy stable sort, and the exact CP-ALS fixed
+point of an exactly low-rank tensor.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "alto_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MAX_MODES = 16
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile the C oracle with gcc (host only)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_oracle(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.oracle_plan.argtypes = [ctypes.c_int, P, P, P, P]
+        lib.oracle_plan.restype = ctypes.c_int
+        lib.oracle_encode.argtypes = [ctypes.c_int, P, i64, P, P]
+        lib.oracle_encode.restype = i64
+        lib.oracle_decode.argtypes = [ctypes.c_int, P, i64, P, P]
+        lib.oracle_decode.restype = ctypes.c_int
+        lib.oracle_order.argtypes = [i64, P, P]
+        lib.oracle_order.restype = ctypes.c_int
+        lib.oracle_partition.argtypes = [ctypes.c_int, P, i64, P, i64, P, P]
+        lib.oracle_partition.restype = ctypes.c_int
+        lib.oracle_mttkrp.argtypes = [ctypes.c_int, P, i64, P, P, ctypes.c_int, P, ctypes.c_int, P]
+        lib.oracle_mttkrp.restype = ctypes.c_int
+        lib.oracle_mttkrp_rows.argtypes = [ctypes.c_int, P, i64, P, P, ctypes.c_int, P, ctypes.c_int, i64, P, P]
+        lib.oracle_mttkrp_rows.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(dims) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(dims, dtype=np.uint64))
+
+
+def plan(dims):
+    """(B, nbits[N], pos[N,64], masks[N] as Python ints) of the ALTO index."""
+    d = _dims(dims)
+    n = len(d)
+    nbits = np.zeros(n, dtype=np.int32)
+    pos = np.zeros((n, 64), dtype=np.int32)
+    masks = np.zeros((n, 2), dtype=np.uint64)
+    total = _L().oracle_plan(n, _ptr(d), _ptr(nbits), _ptr(pos), _ptr(masks))
+    if total < 0:
+        raise ValueError("invalid dimensions or index wider than 128 bits")
+    m = [int(masks[k, 0]) | (int(masks[k, 1]) << 64) for k in range(n)]
+    return total, nbits, pos, m
+
+
+def encode(dims, coords: np.ndarray) -> np.ndarray:
+    """ALTO index of every nonzero as an (M, 2) uint64 array (lo, hi)."""
+    d = _dims(dims)
+    c = np.ascontiguousarray(coords, dtype=np.int64)
+    m = c.shape[1]
+    keys = np.zeros((m, 2), dtype=np.uint64)
+    rc = _L().oracle_encode(len(d), _ptr(d), m, _ptr(c), _ptr(keys))
+    if rc != 0:
+        raise ValueError(f"coordinate out of range at nonzero {rc - 1}" if rc > 0 else "invalid dimensions")
+    return keys
+
+
+def decode(dims, keys: np.ndarray) -> np.ndarray:
+    d = _dims(dims)
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    m = k.shape[0]
+    out = np.zeros((len(d), m), dtype=np.int64)
+    if _L().oracle_decode(len(d), _ptr(d), m, _ptr(k), _ptr(out)) != 0:
+        raise ValueError("invalid dimensions")
+    return out
+
+
+def order(keys: np.ndarray) -> np.ndarray:
+    """Stable ordering permutation of the nonzeros by ALTO index."""
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    m = k.shape[0]
+    perm = np.zeros(m, dtype=np.int64)
+    if _L().oracle_order(m, _ptr(k), _ptr(perm)) != 0:
+        raise MemoryError("oracle_order")
+    return perm
+
+
+def partition(dims, sorted_keys: np.ndarray, nseg: int):
+    """(starts[L+1], intervals[L, N, 2]) of ``nseg`` balanced line segments."""
+    d = _dims(dims)
+    k = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
+    m = k.shape[0]
+    starts = np.zeros(nseg + 1, dtype=np.int64)
+    iv = np.zeros((nseg, len(d), 2), dtype=np.uint64)
+    if _L().oracle_partition(len(d), _ptr(d), m, _ptr(k), int(nseg), _ptr(starts), _ptr(iv)) != 0:
+        raise ValueError("invalid partition request")
+    return starts, iv
+
+
+def _factor_ptrs(factors, rank, dims):
+    fs = []
+    for n, f in enumerate(factors):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        if f.shape != (int(dims[n]), rank):
+            raise ValueError(f"factor {n} has shape {f.shape}, expected {(int(dims[n]), rank)}")
+        fs.append(f)
+    arr = (ctypes.c_void_p * len(fs))(*[f.ctypes.data for f in fs])
+    return fs, arr
+
+
+def mttkrp(dims, coords: np.ndarray, vals: np.ndarray, factors, mode: int) -> np.ndarray:
+    """FP64 MTTKRP of mode ``mode``: X_(mode) times the Khatri-Rao product of
+    the other factors, as a plain loop over the COO nonzeros."""
+    d = _dims(dims)
+    c = np.ascontiguousarray(coords, dtype=np.int64)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    rank = int(np.asarray(factors[0]).shape[1])
+    keep, arr = _factor_ptrs(factors, rank, d)
+    out = np.zeros((int(d[mode]), rank), dtype=np.float64)
+    rc = _L().oracle_mttkrp(len(d), _ptr(d), v.shape[0], _ptr(c), _ptr(v), rank, arr, int(mode), _ptr(out))
+    if rc != 0:
+        raise ValueError("invalid mode or rank")
+    del keep
+    return out
+
+
+def mttkrp_rows(dims, coords, vals, factors, mode: int, rows) -> np.ndarray:
+    """Rows ``rows`` (sorted, distinct) of the FP64 MTTKRP of mode ``mode``."""
+    d = _dims(dims)
+    c = np.ascontiguousarray(coords, dtype=np.int64)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    if r.size > 1 and not np.all(np.diff(r) > 0):
+        raise ValueError("rows must be sorted and distinct")
+    rank = int(np.asarray(factors[0]).shape[1])
+    keep, arr = _factor_ptrs(factors, rank, d)
+    out = np.zeros((r.shape[0], rank), dtype=np.float64)
+    rc = _L().oracle_mttkrp_rows(
+        len(d), _ptr(d), v.shape[0], _ptr(c), _ptr(v), rank, arr, int(mode), r.shape[0], _ptr(r), _ptr(out)
+    )
+    if rc != 0:
+        raise ValueError("invalid mode or rank")
+    del keep
+    return out
+
+
+def _solve_spd_or_pinv(V: np.ndarray, M: np.ndarray):
+    """Return (M V^+, used_cholesky).  V^+ is applied through a Cholesky
+    factorisation when V is symmetric positive definite with no pivot
+    L_ii^2 at or below R*eps*max(diag V), else through the symmetric
+    eigendecomposition with eigenvalues at or below R*eps*max|eig| dropped."""
+    R = V.shape[0]
+    eps = np.finfo(np.float64).eps
+    try:
+        L = np.linalg.cholesky(V)
+        # a pivot at rounding level means V is singular in exact arithmetic
+        if np.min(np.diag(L)) ** 2 <= R * eps * np.max(np.diag(V)):
+            raise np.linalg.LinAlgError("numerically singular")
+        # A V = M  <=>  V A^T = M^T  (V symmetric)
+        Y = np.linalg.solve(L, M.T)
+        X = np.linalg.solve(L.T, Y)
+        return X.T, True
+    except np.linalg.LinAlgError:
+        w, Q = np.linalg.eigh(V)
+        cut = R * eps * max(float(np.max(np.abs(w))), 0.0)
+        inv = np.where(w > cut, 1.0 / np.where(w > cut, w, 1.0), 0.0)
+        return (M @ Q) * inv @ Q.T, False
+
+
+def als_sweep(dims, coords, vals, factors, return_mttkrp: bool = False):
+    """One CP-ALS sweep (all modes, in order 0..N-1) in FP64.
+
+    For each mode n: Grams of the other factors, V = their Hadamard product,
+    M = MTTKRP(n), A^(n) = M V^+ (Cholesky, pseudo-inverse fallback),
+    lambda = column 2-norms of A^(n), columns divided by lambda (a zero
+    column stays zero with lambda = 0).  Returns (factors, lambda of the last
+    mode, per-mode flags of whether Cholesky succeeded[, per-mode M])."""
+    A = [np.array(f, dtype=np.float64, copy=True) for f in factors]
+    N = len(A)
+    R = A[0].shape[1]
+    lam = np.zeros(R)
+    chol_ok = []
+    Ms = []
+    for n in range(N):
+        V = np.ones((R, R))
+        for m in range(N):
+            if m != n:
+                V *= A[m].T @ A[m]
+        M = mttkrp(dims, coords, vals, A, n)
+        if return_mttkrp:
+            Ms.append(M)
+        An, ok = _solve_spd_or_pinv(V, M)
+        chol_ok.append(ok)
+        lam = np.sqrt(np.sum(An * An, axis=0))
+        safe = np.where(lam > 0, lam, 1.0)
+        A[n] = An / safe
+    if return_mttkrp:
+        return A, lam, chol_ok, Ms
+    return A, lam, chol_ok
