@@ -1,0 +1,247 @@
+/*
+ * alto.h -- C ABI of the MI355X (gfx950) ALTO sparse-tensor library.
+ *
+ * Implements, for one GPU, the hot path of "Accelerating Sparse Tensor
+ * Decomposition Using Adaptive Linearized Representation" (Laukemann et al.,
+ * arXiv 2403.06348):
+ *   - ALTO format generation: linearization of every nonzero's coordinates
+ *     into one bit-interleaved index (Sec. "ALTO Tensor Generation", Eq. 1,
+ *     Fig. "alto_linear"(a)), ordering by that index, and partitioning of
+ *     the ordered line into nnz-balanced segments with per-segment mode
+ *     intervals (Sec. "Workload Partitioning and Scheduling");
+ *   - MTTKRP on any mode over the single ALTO copy, with de-linearization by
+ *     mask extraction (Fig. "alto_linear"(b)) and adaptive conflict
+ *     resolution (Sec. "Adaptive Conflict Resolution");
+ *   - one CP-ALS sweep (Algorithm "alg:cp-als").
+ *
+ * Conventions for every call
+ *   - Pointers are DEVICE pointers unless marked "host".  Arrays of
+ *     per-mode device pointers (coords, factors) are host arrays.
+ *   - Coordinates and modes are 0-based.  Matrices are row-major.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it; calls do not synchronize it
+ *     unless stated.  A handle must not be used from two streams at once.
+ *   - Every call returns an alto_status; on failure alto_last_error()
+ *     (thread-local) describes it.  Argument errors are detected on the
+ *     host before anything is enqueued.
+ *   - Limits: 1 <= nmodes <= ALTO_MAX_MODES; 1 <= dims[n] < 2^32; the
+ *     index width sum_n ceil(log2 dims[n]) <= 128 bits; nnz < 2^40;
+ *     rank a multiple of 4 in 4..ALTO_MAX_RANK.
+ */
+#ifndef ALTO_MI355X_H
+#define ALTO_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ALTO_MAX_MODES 8
+#define ALTO_MAX_RANK 128
+
+typedef struct alto_tensor *alto_handle;
+
+typedef enum {
+    ALTO_OK = 0,
+    ALTO_ERR_ARG = 1,          /* invalid argument (detected on the host)            */
+    ALTO_ERR_COORD_RANGE = 2,  /* a coordinate lies outside [0, dims[n])              */
+    ALTO_ERR_INDEX_BITS = 3,   /* sum of index bits exceeds 128                       */
+    ALTO_ERR_OOM = 4,          /* device allocation failed                            */
+    ALTO_ERR_HIP = 5,          /* a HIP runtime call failed                           */
+    ALTO_ERR_NOT_SPD = 6,      /* WARNING: V was not positive definite for at least   */
+                               /* one mode; the pseudo-inverse was used, results valid */
+    ALTO_ERR_STATE = 7,        /* handle not usable (NULL, freed, wrong object)       */
+    ALTO_ERR_BUDGET = 8        /* serving: job can never fit the memory budget        */
+} alto_status;
+
+typedef enum { ALTO_F32 = 0, ALTO_BF16 = 1 } alto_dtype;
+
+/* Conflict resolution of MTTKRP updates (Sec. "Adaptive Conflict Resolution").
+ * ALTO_CR_TILE: updates of a tile of consecutive nonzeros are merged per output
+ *   row in LDS (the GPU form of the per-partition temporary rows), then each
+ *   merged row is added to the output once.
+ * ALTO_CR_RUN: runs of consecutive nonzeros with the same output row are merged
+ *   in registers and added to the output directly (the GPU form of the
+ *   output-oriented traversal with atomics only where rows are shared).
+ * ALTO_CR_AUTO: chosen per mode from the fiber reuse nnz / dims[mode]. */
+typedef enum { ALTO_CR_AUTO = 0, ALTO_CR_TILE = 1, ALTO_CR_RUN = 2 } alto_conflict;
+
+/* Where the merged output rows are summed.
+ * ALTO_ACC_F64: in an FP64 buffer (handle workspace), rounded once to FP32.
+ * ALTO_ACC_F32: directly in the FP32 output with FP32 atomics. */
+typedef enum { ALTO_ACC_DEFAULT = 0, ALTO_ACC_F64 = 1, ALTO_ACC_F32 = 2 } alto_accumulate;
+
+/* Tunable launch plan of one MTTKRP.  Zero fields take the library default
+ * (or the autotuned value when one was recorded for the handle and mode). */
+typedef struct {
+    int conflict;        /* alto_conflict                                          */
+    int tile_nnz;        /* nonzeros per workgroup tile (line segment length)      */
+    int block_threads;   /* 256, 512 or 1024                                       */
+    int table_slots;     /* LDS merge-table rows (power of two), TILE only         */
+    int accumulate;      /* alto_accumulate                                        */
+} alto_mttkrp_plan;
+
+/* Host-side description of a handle (see alto_info). */
+typedef struct {
+    int nmodes;
+    int index_bits;        /* B = sum_n ceil(log2 dims[n])                           */
+    int index_words;       /* 1 (B <= 64) or 2 (64 < B <= 128) 64-bit words          */
+    int nbits[ALTO_MAX_MODES];
+    uint64_t dims[ALTO_MAX_MODES];
+    uint64_t mask_lo[ALTO_MAX_MODES];  /* bits of the index holding mode n        */
+    uint64_t mask_hi[ALTO_MAX_MODES];
+    uint64_t nnz;
+    uint64_t device_bytes; /* device memory owned by the handle right now          */
+} alto_info_t;
+
+/* ---------------------------------------------------------------- format */
+
+/*
+ * Plan only (host, no GPU needed): bit layout of the ALTO index for `dims`.
+ * Mode n gets ceil(log2 dims[n]) bits; bit group l holds bit l of every mode
+ * with more than l bits, shortest mode lowest (Sec. "ALTO Tensor
+ * Generation", Eq. 1).  Fills every field of *out except nnz/device_bytes.
+ * Errors: ALTO_ERR_ARG, ALTO_ERR_INDEX_BITS.
+ */
+alto_status alto_plan_dims(int nmodes, const uint64_t *dims /*host[nmodes]*/, alto_info_t *out /*host*/);
+
+/*
+ * Host reference of the extraction used on the device: decodes `count` ALTO
+ * indices keys[2*i], keys[2*i+1] (lo, hi words; host) into coords[n*count+i]
+ * (host, int64) with the same compiled code path as the GPU kernels.
+ */
+alto_status alto_plan_decode_host(const alto_info_t *plan, uint64_t count, const uint64_t *keys /*host*/,
+                                  int64_t *coords /*host*/);
+
+/*
+ * Build an ALTO tensor (Sec. "ALTO Tensor Generation"): linearize every
+ * nonzero, order the nonzeros by ALTO index (stable radix sort on the GPU)
+ * and partition the line.  coords[n] is a device array of nnz int64
+ * coordinates of mode n, vals a device array of nnz FP32 values.  The
+ * library copies what it needs; the caller may free its inputs once the
+ * stream has passed this call.  Duplicate coordinates stay separate
+ * nonzeros.  nnz = 0 is valid.
+ * Synchronizes `stream` once at the end to read the device coordinate-range
+ * flag.  Errors: ALTO_ERR_ARG, ALTO_ERR_INDEX_BITS, ALTO_ERR_COORD_RANGE (no
+ * handle is returned), ALTO_ERR_OOM, ALTO_ERR_HIP.
+ */
+alto_status alto_build(int nmodes, const uint64_t *dims /*host[nmodes]*/, uint64_t nnz,
+                       const int64_t *const *coords /*host[nmodes] of device ptrs*/, const float *vals,
+                       void *stream, alto_handle *out /*host*/);
+
+/* Host description of a built tensor. */
+alto_status alto_info(alto_handle h, alto_info_t *out /*host*/);
+
+/*
+ * Copy the ordered ALTO tensor out: keys_out gets nnz * index_words uint64
+ * (word w of nonzero x at keys_out[x*index_words + w], low word first),
+ * vals_out gets nnz FP32 values in the same order.  Either may be NULL.
+ */
+alto_status alto_export(alto_handle h, uint64_t *keys_out, float *vals_out, void *stream);
+
+/*
+ * De-linearize `count` ALTO indices (device, layout as in alto_export) with
+ * the handle's masks (Fig. "alto_linear"(b)): coords_out[n*count + i]
+ * (device int64).
+ */
+alto_status alto_decode(alto_handle h, uint64_t count, const uint64_t *keys, int64_t *coords_out, void *stream);
+
+/*
+ * Partition the ordered line into nseg nnz-balanced segments (Sec.
+ * "Workload Partitioning and Scheduling"): starts_out[l] = floor(l*nnz/nseg)
+ * for l = 0..nseg (device int64), and the closed mode intervals of every
+ * segment, intervals_out[(l*nmodes + n)*2 + 0/1] = min/max mode-n
+ * coordinate (device uint64); an empty segment gets (UINT64_MAX, 0).
+ */
+alto_status alto_partition(alto_handle h, int64_t nseg, int64_t *starts_out, uint64_t *intervals_out,
+                           void *stream);
+
+/* Release the handle and every buffer it owns (after its stream work). */
+alto_status alto_free(alto_handle h);
+
+/* ---------------------------------------------------------------- MTTKRP */
+
+/*
+ * MTTKRP of mode `mode` (Algorithm "alg:cp-als", MTTKRP line; sequential
+ * MTTKRP-ALTO algorithm): out = X_(mode) (A^(0) KRP ... A^(N-1)) with the
+ * mode's own factor left out, i.e. for every nonzero x,
+ *   out[i_mode(x), r] += val(x) * prod_{m != mode} A^(m)[i_m(x), r].
+ * factors[m] (device, row-major dims[m] x rank, FP32 or BF16 per fdt;
+ * factors[mode] is not read and may be NULL).  out (device FP32,
+ * dims[mode] x rank) is overwritten.  Accumulation is FP32 (partial rows) with
+ * the final per-row sum in FP32 or FP64 per plan.  May allocate handle
+ * workspace on first use of a (mode, rank).
+ */
+alto_status alto_mttkrp(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors,
+                        float *out, void *stream);
+
+/* Same, with an explicit launch plan (NULL = defaults). */
+alto_status alto_mttkrp_ex(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors,
+                           float *out, const alto_mttkrp_plan *plan, void *stream);
+
+/* Plan that alto_mttkrp would use for (mode, rank, fdt) (host). */
+alto_status alto_mttkrp_get_plan(alto_handle h, int mode, int rank, alto_dtype fdt, alto_mttkrp_plan *out);
+
+/*
+ * Autotune (project-written): times candidate plans for (mode, rank, fdt) on
+ * `stream` with the given factors (out is used as scratch and ends with a
+ * valid result), records the fastest in the handle and in the process-wide
+ * cache keyed by (nmodes, rank, index words, fdt, reuse class), and returns it.
+ * Synchronizes the stream.
+ */
+alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors,
+                          float *out, void *stream, alto_mttkrp_plan *chosen /*host, may be NULL*/);
+
+/*
+ * Many MTTKRPs in one persistent launch: item j computes MTTKRP of mode
+ * modes[j] of handle hs[j] with rank ranks[j] and factor type fdts[j] from
+ * factors[j][*] into outs[j].  Handles may differ in order, dims, index width
+ * and nnz; all items' tiles form one work list that resident workgroups
+ * drain.  Results are those of alto_mttkrp up to FP32 summation order.
+ */
+alto_status alto_mttkrp_batched(int count, const alto_handle *hs /*host*/, const int *modes /*host*/,
+                                const int *ranks /*host*/, const int *fdts /*host*/,
+                                const void *const *const *factors /*host[count] of host[nmodes]*/,
+                                float *const *outs /*host[count]*/, void *stream);
+
+/* ---------------------------------------------------------------- CP-ALS */
+
+/*
+ * One CP-ALS sweep (Algorithm "alg:cp-als", one pass of the outer loop):
+ * for n = 0..N-1: V = Hadamard product of the Grams A^(m)T A^(m), m != n
+ * (FP64); M = MTTKRP(n); A^(n) = M V^-1 via an FP64 Cholesky factorisation of
+ * V (symmetric-eigen pseudo-inverse when V is not positive definite, which
+ * returns ALTO_ERR_NOT_SPD as a warning); lambda = column 2-norms of A^(n)
+ * (FP64); columns of A^(n) divided by lambda (a zero column stays zero).
+ * factors[m] (device FP32, dims[m] x rank) are updated in place; lambda
+ * (device FP64 [rank]) receives the last mode's norms.  fdt = ALTO_BF16 makes
+ * the MTTKRPs read BF16 (round-to-nearest-even) shadow copies of the factors,
+ * kept in handle workspace and refreshed after every update; Grams, solve and
+ * lambda stay FP64 from the FP32 masters.
+ * Everything stays on the GPU; the call is graph-capturable after a first
+ * call has allocated the workspace.
+ */
+alto_status cpd_als_sweep(alto_handle h, int rank, float *const *factors, double *lambda, void *stream);
+alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *const *factors, double *lambda,
+                             void *stream);
+
+/*
+ * Status flags of the last sweep on `stream` (host, synchronizes the stream):
+ * bit n set when mode n used the pseudo-inverse fallback.
+ */
+alto_status alto_sweep_flags(alto_handle h, void *stream, uint32_t *flags /*host*/);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Thread-local description of the last failure (never NULL). */
+const char *alto_last_error(void);
+
+/* Library version string, e.g. "alto-mi355x 1.0 gfx950". */
+const char *alto_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALTO_MI355X_H */

@@ -1,0 +1,435 @@
+// One CP-ALS sweep on the GPU (Algorithm "alg:cp-als" of the paper).
+//
+// Per mode n:  V = Hadamard product of the Grams of the other factors;
+// M = MTTKRP(n); A^(n) = M V^-1; lambda = column 2-norms of A^(n); columns
+// divided by lambda.  The R x R work (Grams, Cholesky, inverse, lambda) is
+// FP64; the I x R matrices are FP32 (FP64 arithmetic, FP32 storage).
+//
+// Kernels
+//   k_gram_partial   partial Grams A^T A of row chunks (FP64 accumulation)
+//   k_gram_reduce    sum of the partials (fixed order, deterministic)
+//   k_als_prepare    one workgroup: V, Cholesky V = L L^T, W = L^-T L^-1;
+//                    if a pivot is at rounding level, W = pseudo-inverse from
+//                    a cyclic Jacobi eigendecomposition (flag bit n set)
+//   k_als_apply      A^(n) = M W row by row, plus partial Grams of A^(n)
+//   k_als_finalize   lambda_r = sqrt(G_rr), Gram of the normalized factor
+//   k_als_normalize  A^(n)(:, r) /= lambda_r, BF16 shadow refresh
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "alto_internal.h"
+#include "device_util.h"
+#include "memory.h"
+#include "mttkrp.h"
+
+namespace alto {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kChunk = 32;        // rows staged per step
+constexpr int kPartials = 512;    // partial Gram blocks
+constexpr int kMaxSweepRank = 64;
+
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));  // inf / nan
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+
+// Accumulate sum_i X[i][r] X[i][s] over rows staged in LDS (double).
+template <int ENT>
+__device__ inline void gram_accumulate(const double *sx, int rows, int R, const int *re, const int *se, double *acc) {
+    for (int i = 0; i < rows; i++) {
+        const double *x = sx + i * R;
+#pragma unroll
+        for (int j = 0; j < ENT; j++)
+            if (re[j] >= 0) acc[j] = fma(x[re[j]], x[se[j]], acc[j]);
+    }
+}
+
+template <int ENT>
+__global__ __launch_bounds__(kThreads) void k_gram_partial(const float *__restrict__ A, uint64_t I, int R,
+                                                           double *__restrict__ partials) {
+    __shared__ double sx[kChunk * kMaxSweepRank];
+    int re[ENT], se[ENT];
+    double acc[ENT];
+#pragma unroll
+    for (int j = 0; j < ENT; j++) {
+        const int e = threadIdx.x + j * kThreads;
+        re[j] = e < R * R ? e / R : -1;
+        se[j] = e < R * R ? e % R : 0;
+        acc[j] = 0.0;
+    }
+    const uint64_t per = (I + gridDim.x - 1) / gridDim.x;
+    const uint64_t a = (uint64_t)blockIdx.x * per;
+    const uint64_t b = a + per < I ? a + per : I;
+    for (uint64_t c = a; c < b; c += kChunk) {
+        const int rows = (int)((b - c) < (uint64_t)kChunk ? (b - c) : (uint64_t)kChunk);
+        for (int t = threadIdx.x; t < rows * R; t += kThreads) sx[t] = (double)A[c * R + t];
+        __syncthreads();
+        gram_accumulate<ENT>(sx, rows, R, re, se, acc);
+        __syncthreads();
+    }
+    double *o = partials + (uint64_t)blockIdx.x * R * R;
+#pragma unroll
+    for (int j = 0; j < ENT; j++)
+        if (re[j] >= 0) o[re[j] * R + se[j]] = acc[j];
+}
+
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(const double *__restrict__ partials, int np, int R,
+                                                          double *__restrict__ G) {
+    for (int e = threadIdx.x; e < R * R; e += kThreads) {
+        double s = 0.0;
+        for (int p = 0; p < np; p++) s += partials[(uint64_t)p * R * R + e];
+        G[e] = s;
+    }
+}
+
+// Single workgroup.  grams: N x R x R; W: R x R output; flags bit n on fallback.
+__global__ __launch_bounds__(kThreads) void k_als_prepare(const double *__restrict__ grams, int N, int n, int R,
+                                                          double *__restrict__ W, uint32_t *flags) {
+    extern __shared__ double sm[];
+    double *V = sm;           // R x R
+    double *L = sm + R * R;   // R x R (Cholesky factor, then inverse / eigenvectors)
+    double *T = L + R * R;    // R x R scratch
+    __shared__ int not_spd;
+    __shared__ double vmax;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < R * R; e += kThreads) {
+        double v = 1.0;
+        for (int m = 0; m < N; m++)
+            if (m != n) v *= grams[(uint64_t)m * R * R + e];
+        V[e] = v;
+        L[e] = 0.0;
+    }
+    if (tid == 0) not_spd = 0;
+    __syncthreads();
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int k = 0; k < R; k++) mx = fmax(mx, V[k * R + k]);
+        vmax = mx;
+    }
+    __syncthreads();
+    const double tol = (double)R * 2.220446049250313e-16 * vmax;
+    // left-looking Cholesky, one column at a time, rows in parallel
+    for (int k = 0; k < R; k++) {
+        for (int i = k + tid; i < R; i += kThreads) {
+            double t = V[i * R + k];
+            for (int j = 0; j < k; j++) t -= L[i * R + j] * L[k * R + j];
+            T[i] = t;
+        }
+        __syncthreads();
+        const double d = T[k];
+        if (!(d > tol)) {
+            if (tid == 0) not_spd = 1;
+            __syncthreads();
+            break;
+        }
+        const double lk = sqrt(d);
+        for (int i = k + tid; i < R; i += kThreads) L[i * R + k] = (i == k) ? lk : T[i] / lk;
+        __syncthreads();
+    }
+    __syncthreads();
+    if (!not_spd) {
+        // columns of L^-1 by forward substitution (column j per thread)
+        double *Li = T;  // reuse as R x R
+        for (int j = tid; j < R; j += kThreads) {
+            for (int i = 0; i < R; i++) {
+                double s = (i == j) ? 1.0 : 0.0;
+                for (int k = j; k < i; k++) s -= L[i * R + k] * Li[k * R + j];
+                Li[i * R + j] = (i < j) ? 0.0 : s / L[i * R + i];
+            }
+        }
+        __syncthreads();
+        // W = L^-T L^-1
+        for (int e = tid; e < R * R; e += kThreads) {
+            const int r = e / R, s = e % R;
+            double w = 0.0;
+            for (int k = (r > s ? r : s); k < R; k++) w += Li[k * R + r] * Li[k * R + s];
+            W[e] = w;
+        }
+        return;
+    }
+    // ---- fallback: symmetric eigendecomposition by cyclic Jacobi rotations
+    double *Aj = T;  // working copy
+    double *Q = L;
+    for (int e = tid; e < R * R; e += kThreads) {
+        Aj[e] = V[e];
+        Q[e] = (e / R == e % R) ? 1.0 : 0.0;
+    }
+    __shared__ double cs[2];
+    __shared__ double off;
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; sweep++) {
+        if (tid == 0) {
+            double o = 0.0, d = 0.0;
+            for (int p = 0; p < R; p++)
+                for (int q = 0; q < R; q++) {
+                    const double v = Aj[p * R + q] * Aj[p * R + q];
+                    if (p == q) d += v;
+                    else o += v;
+                }
+            off = (o <= 1e-30 * d) ? -1.0 : o;
+        }
+        __syncthreads();
+        if (off < 0) break;
+        for (int p = 0; p < R - 1; p++) {
+            for (int q = p + 1; q < R; q++) {
+                if (tid == 0) {
+                    const double apq = Aj[p * R + q];
+                    double c = 1.0, s = 0.0;
+                    if (apq != 0.0) {
+                        const double theta = (Aj[q * R + q] - Aj[p * R + p]) / (2.0 * apq);
+                        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                    }
+                    cs[0] = c;
+                    cs[1] = s;
+                }
+                __syncthreads();
+                const double c = cs[0], s = cs[1];
+                if (s != 0.0) {
+                    for (int k = tid; k < R; k += kThreads) {  // columns p, q
+                        const double akp = Aj[k * R + p], akq = Aj[k * R + q];
+                        Aj[k * R + p] = c * akp - s * akq;
+                        Aj[k * R + q] = s * akp + c * akq;
+                    }
+                    __syncthreads();
+                    for (int k = tid; k < R; k += kThreads) {  // rows p, q
+                        const double apk = Aj[p * R + k], aqk = Aj[q * R + k];
+                        Aj[p * R + k] = c * apk - s * aqk;
+                        Aj[q * R + k] = s * apk + c * aqk;
+                        const double qkp = Q[k * R + p], qkq = Q[k * R + q];
+                        Q[k * R + p] = c * qkp - s * qkq;
+                        Q[k * R + q] = s * qkp + c * qkq;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    __shared__ double emax;
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int k = 0; k < R; k++) mx = fmax(mx, fabs(Aj[k * R + k]));
+        emax = mx;
+        atomicOr(flags, 1u << n);
+    }
+    __syncthreads();
+    const double cut = (double)R * 2.220446049250313e-16 * emax;
+    for (int e = tid; e < R * R; e += kThreads) {
+        const int r = e / R, s = e % R;
+        double w = 0.0;
+        for (int k = 0; k < R; k++) {
+            const double lam = Aj[k * R + k];
+            if (lam > cut) w += Q[r * R + k] * Q[s * R + k] / lam;
+        }
+        W[e] = w;
+    }
+}
+
+// A = M W (FP64 arithmetic, FP32 store) and partial Grams of the stored A.
+template <int ENT>
+__global__ __launch_bounds__(kThreads) void k_als_apply(const float *__restrict__ M, const double *__restrict__ W,
+                                                        float *__restrict__ A, uint64_t I, int R,
+                                                        double *__restrict__ partials) {
+    __shared__ double sw[kMaxSweepRank * kMaxSweepRank];
+    __shared__ double sm[kChunk * kMaxSweepRank];
+    __shared__ double sa[kChunk * kMaxSweepRank];
+    for (int e = threadIdx.x; e < R * R; e += kThreads) sw[e] = W[e];
+    int re[ENT], se[ENT];
+    double acc[ENT];
+#pragma unroll
+    for (int j = 0; j < ENT; j++) {
+        const int e = threadIdx.x + j * kThreads;
+        re[j] = e < R * R ? e / R : -1;
+        se[j] = e < R * R ? e % R : 0;
+        acc[j] = 0.0;
+    }
+    const uint64_t per = (I + gridDim.x - 1) / gridDim.x;
+    const uint64_t a = (uint64_t)blockIdx.x * per;
+    const uint64_t b = a + per < I ? a + per : I;
+    __syncthreads();
+    for (uint64_t c = a; c < b; c += kChunk) {
+        const int rows = (int)((b - c) < (uint64_t)kChunk ? (b - c) : (uint64_t)kChunk);
+        for (int t = threadIdx.x; t < rows * R; t += kThreads) sm[t] = (double)M[c * R + t];
+        __syncthreads();
+        for (int t = threadIdx.x; t < rows * R; t += kThreads) {
+            const int i = t / R, s = t % R;
+            double v = 0.0;
+            for (int r = 0; r < R; r++) v = fma(sm[i * R + r], sw[r * R + s], v);
+            const float f = (float)v;
+            A[c * R + t] = f;
+            sa[t] = (double)f;
+        }
+        __syncthreads();
+        gram_accumulate<ENT>(sa, rows, R, re, se, acc);
+        __syncthreads();
+    }
+    double *o = partials + (uint64_t)blockIdx.x * R * R;
+#pragma unroll
+    for (int j = 0; j < ENT; j++)
+        if (re[j] >= 0) o[re[j] * R + se[j]] = acc[j];
+}
+
+__global__ __launch_bounds__(kThreads) void k_als_finalize(const double *__restrict__ partials, int np, int R,
+                                                           double *__restrict__ Gn, double *__restrict__ lam_ws,
+                                                           double *__restrict__ lam_out) {
+    __shared__ double lam[kMaxSweepRank];
+    __shared__ double G[kMaxSweepRank * kMaxSweepRank];
+    for (int e = threadIdx.x; e < R * R; e += kThreads) {
+        double s = 0.0;
+        for (int p = 0; p < np; p++) s += partials[(uint64_t)p * R * R + e];
+        G[e] = s;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += kThreads) {
+        const double l = sqrt(fmax(G[r * R + r], 0.0));
+        lam[r] = l;
+        lam_ws[r] = l;
+        if (lam_out) lam_out[r] = l;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * R; e += kThreads) {
+        const int r = e / R, s = e % R;
+        const double d = lam[r] * lam[s];
+        Gn[e] = d > 0.0 ? G[e] / d : 0.0;
+    }
+}
+
+__global__ void k_als_normalize(float *__restrict__ A, uint64_t I, int R, const double *__restrict__ lam,
+                                uint16_t *__restrict__ shadow) {
+    const uint64_t n = I * R;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const double l = lam[t % R];
+        float v = A[t];
+        if (l > 0.0) v = (float)((double)v / l);
+        A[t] = v;
+        if (shadow) shadow[t] = f32_to_bf16_rne(v);
+    }
+}
+
+__global__ void k_to_bf16(const float *__restrict__ A, uint64_t n, uint16_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) out[t] = f32_to_bf16_rne(A[t]);
+}
+
+int ent_for(int R) {
+    const int e = (R * R + kThreads - 1) / kThreads;
+    int p = 1;
+    while (p < e) p <<= 1;
+    return p;
+}
+
+#define ALTO_ENT_DISPATCH(ent, KERNEL, ...)                                               \
+    switch (ent) {                                                                        \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                        \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                        \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                        \
+        case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                        \
+        default: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                      \
+    }
+
+unsigned partial_blocks(uint64_t I) {
+    uint64_t p = (I + 255) / 256;
+    if (p > kPartials) p = kPartials;
+    if (p < 1) p = 1;
+    return (unsigned)p;
+}
+
+}  // namespace
+}  // namespace alto
+
+using namespace alto;
+
+extern "C" {
+
+alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *const *factors, double *lambda,
+                             void *stream) {
+    ALTO_CHECK_HANDLE(h);
+    const int N = h->info.nmodes;
+    const int R = rank;
+    if (R < 4 || R > kMaxSweepRank || R % 4) return fail(ALTO_ERR_ARG, "sweep rank must be a multiple of 4 in 4..64");
+    if (fdt != ALTO_F32 && fdt != ALTO_BF16) return fail(ALTO_ERR_ARG, "bad factor dtype");
+    if (!factors || !lambda) return fail(ALTO_ERR_ARG, "factors/lambda is NULL");
+    for (int m = 0; m < N; m++) {
+        if (!factors[m]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(m) + "] is NULL");
+        if ((uintptr_t)factors[m] & 15) return fail(ALTO_ERR_ARG, "factors must be 16-byte aligned");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t maxI = 0;
+    for (int m = 0; m < N; m++) maxI = h->info.dims[m] > maxI ? h->info.dims[m] : maxI;
+    const size_t rr = (size_t)R * R;
+    const size_t need = (size_t)(N * rr + rr + (size_t)kPartials * rr + R) * 8;
+    alto_status st = ensure_ws(&h->ws_sweep, &h->ws_sweep_bytes, need);
+    if (st != ALTO_OK) return st;
+    st = ensure_ws((void **)&h->ws_m, &h->ws_m_bytes, (size_t)maxI * R * 4);
+    if (st != ALTO_OK) return st;
+    size_t flag_bytes = h->ws_flags ? 256 : 0;
+    st = ensure_ws((void **)&h->ws_flags, &flag_bytes, 256);
+    if (st != ALTO_OK) return st;
+    if (fdt == ALTO_BF16) {
+        for (int m = 0; m < N; m++) {
+            st = ensure_ws((void **)&h->ws_bf16[m], &h->ws_bf16_bytes[m], (size_t)h->info.dims[m] * R * 2);
+            if (st != ALTO_OK) return st;
+        }
+    }
+    double *grams = (double *)h->ws_sweep;
+    double *W = grams + N * rr;
+    double *partials = W + rr;
+    double *lam_ws = partials + (size_t)kPartials * rr;
+    const int ent = ent_for(R);
+
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, h->ws_flags, (uint64_t)1, 0u);
+    for (int m = 0; m < N; m++) {
+        const uint64_t I = h->info.dims[m];
+        const unsigned P = partial_blocks(I);
+        ALTO_ENT_DISPATCH(ent, k_gram_partial, dim3(P), dim3(kThreads), 0, s, factors[m], I, R, partials);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(1), dim3(kThreads), 0, s, partials, (int)P, R, grams + m * rr);
+        if (fdt == ALTO_BF16)
+            hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(I * R, 256, 16384)), dim3(256), 0, s, factors[m], I * R,
+                               h->ws_bf16[m]);
+    }
+    ALTO_HIP(hipGetLastError());
+    const void *fptr[ALTO_MAX_MODES];
+    for (int m = 0; m < N; m++) fptr[m] = fdt == ALTO_BF16 ? (const void *)h->ws_bf16[m] : (const void *)factors[m];
+    for (int n = 0; n < N; n++) {
+        const uint64_t I = h->info.dims[n];
+        hipLaunchKernelGGL(k_als_prepare, dim3(1), dim3(kThreads), 3 * rr * 8, s, grams, N, n, R, W, h->ws_flags);
+        alto_mttkrp_plan p;
+        st = resolve_plan(h, n, R, fdt, nullptr, &p);
+        if (st != ALTO_OK) return st;
+        st = run_mttkrp(h, n, R, fdt, fptr, h->ws_m, p, s);
+        if (st != ALTO_OK) return st;
+        const unsigned P = partial_blocks(I);
+        ALTO_ENT_DISPATCH(ent, k_als_apply, dim3(P), dim3(kThreads), 0, s, h->ws_m, W, factors[n], I, R, partials);
+        hipLaunchKernelGGL(k_als_finalize, dim3(1), dim3(kThreads), 0, s, partials, (int)P, R, grams + n * rr, lam_ws,
+                           n == N - 1 ? lambda : nullptr);
+        hipLaunchKernelGGL(k_als_normalize, dim3(grid_for(I * R, 256, 16384)), dim3(256), 0, s, factors[n], I, R,
+                           lam_ws, fdt == ALTO_BF16 ? h->ws_bf16[n] : nullptr);
+        ALTO_HIP(hipGetLastError());
+    }
+    return ALTO_OK;
+}
+
+alto_status cpd_als_sweep(alto_handle h, int rank, float *const *factors, double *lambda, void *stream) {
+    return cpd_als_sweep_ex(h, rank, ALTO_F32, factors, lambda, stream);
+}
+
+alto_status alto_sweep_flags(alto_handle h, void *stream, uint32_t *flags) {
+    ALTO_CHECK_HANDLE(h);
+    if (!flags) return fail(ALTO_ERR_ARG, "flags is NULL");
+    *flags = 0;
+    if (!h->ws_flags) return ALTO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    ALTO_HIP(hipMemcpyAsync(flags, h->ws_flags, 4, hipMemcpyDeviceToHost, s));
+    ALTO_HIP(hipStreamSynchronize(s));
+    return *flags ? ALTO_ERR_NOT_SPD : ALTO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+// MTTKRP kernel arguments and host helpers shared by the MTTKRP, CP-ALS and
+// batched translation units.
+#pragma once
+
+#include "alto_internal.h"
+
+namespace alto {
+
+constexpr int kMaxProbe = 16;  // LDS table probes before falling back to the output
+
+struct MttkrpArgs {
+    LinePlan lp;
+    const void *fac_other[ALTO_MAX_MODES];  // factors of the other modes, ascending mode order
+    uint32_t last_other[ALTO_MAX_MODES];    // dims - 1 of those modes (gather index clamp)
+    uint32_t dim_out;                       // dims[mode]
+    const uint64_t *keys;
+    const float *vals;
+    float *out32;
+    double *out64;
+    uint64_t nnz;
+    uint64_t ntiles;
+    uint64_t tq, tr;  // nnz / ntiles, nnz % ntiles
+    int mode, rank, nmodes;
+    int tile_merge;   // 1: LDS table merge, 0: direct atomics
+    int use64;        // 1: accumulate into out64
+    int slots_log2;
+    int rec;          // staged record length (u32) per nonzero
+    int xcd_map;      // 1: contiguous tile ranges per XCD
+};
+
+alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt);
+alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan *in,
+                         alto_mttkrp_plan *out);
+alto_status check_mttkrp_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
+                              const float *out);
+alto_status ensure_ws(void **p, size_t *have, size_t need);
+alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
+                       const alto_mttkrp_plan &p, hipStream_t s);
+void fill_args(const alto_tensor *h, int mode, int rank, const void *const *factors, const alto_mttkrp_plan &p,
+               float *out32, double *out64, MttkrpArgs *a);
+size_t lds_bytes(const MttkrpArgs &a, int threads);
+int lpn_for(int rank);
+
+}  // namespace alto

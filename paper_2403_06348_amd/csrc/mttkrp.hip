@@ -1,0 +1,503 @@
+// MTTKRP over the ALTO line (Sec. "ALTO-based Tensor Operations" and
+// "Adaptive Conflict Resolution" of the paper), written for CDNA4.
+//
+// Work decomposition.  The ordered line is cut into L nnz-balanced tiles
+// (tile l = nonzeros floor(l*M/L) .. floor((l+1)*M/L)-1, the paper's line
+// segments).  Resident workgroups drain the tiles; the tiles of each XCD
+// form one contiguous stretch of the line so that neighbouring tiles, which
+// touch nearby factor rows, share that XCD's L2.
+//
+// Inside a workgroup, a "group" of LPN = R/4 (rounded up to a power of two)
+// lanes owns a contiguous run of the tile's nonzeros; lane q of a group
+// handles ranks 4q..4q+3 with 16-byte factor loads.  Per batch of LPN
+// nonzeros each lane loads and de-linearizes one index (mask extraction,
+// Fig. "alto_linear"(b)) and stages (value, output row, other coordinates)
+// in LDS; then the group walks the batch in line order: it gathers the
+// other modes' factor rows, forms val * Hadamard product, and merges
+// consecutive updates of the same output row in registers.  When the output
+// row changes, the merged row is flushed:
+//   - TILE conflict resolution: into an LDS table of partial output rows
+//     keyed by row (open addressing), which is added to the output once per
+//     tile -- the per-partition temporary rows of the paper, keyed by row
+//     instead of indexed by the mode interval, since intervals of skewed
+//     tensors are far wider than LDS;
+//   - RUN conflict resolution: straight to the output with global atomics.
+// The output is an FP32 matrix, or an FP64 accumulation buffer that is
+// rounded to FP32 once at the end (one rounding of a long sum of partials).
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "alto_internal.h"
+#include "device_util.h"
+#include "memory.h"
+#include "mttkrp.h"
+
+namespace alto {
+
+namespace {
+
+__device__ inline uint32_t row_hash(uint32_t r, int log2s) { return (r * 0x9E3779B1u) >> (32 - log2s); }
+
+template <typename FT>
+__device__ inline float4 load4(const void *base, uint64_t elem);
+
+template <>
+__device__ inline float4 load4<float>(const void *base, uint64_t elem) {
+    return *(const float4 *)((const float *)base + elem);
+}
+
+template <>
+__device__ inline float4 load4<uint16_t>(const void *base, uint64_t elem) {
+    const uint2 u = *(const uint2 *)((const uint16_t *)base + elem);
+    float4 f;
+    f.x = __uint_as_float(u.x << 16);
+    f.y = __uint_as_float(u.x & 0xFFFF0000u);
+    f.z = __uint_as_float(u.y << 16);
+    f.w = __uint_as_float(u.y & 0xFFFF0000u);
+    return f;
+}
+
+__device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, const float *acc) {
+    const uint64_t o = (uint64_t)row * a.rank + r0;
+    if (a.use64) {
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (r0 + j < a.rank) unsafeAtomicAdd(a.out64 + o + j, (double)acc[j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (r0 + j < a.rank) unsafeAtomicAdd(a.out32 + o + j, acc[j]);
+    }
+}
+
+// Merge a finished run of updates of `row` into the LDS table (or, when the
+// table has no room within the probe limit, into the output directly).
+__device__ inline void table_add(const MttkrpArgs &a, uint32_t *tkey, float *tval, uint32_t row, int r0,
+                                 const float *acc) {
+    const int log2s = a.slots_log2;
+    const uint32_t smask = (1u << log2s) - 1;
+    uint32_t slot = row_hash(row, log2s);
+    bool placed = false;
+    for (int probe = 0; probe < kMaxProbe; probe++) {
+        const uint32_t old = atomicCAS(tkey + slot, kEmptyRow, row);
+        if (old == kEmptyRow || old == row) {
+            placed = true;
+            break;
+        }
+        slot = (slot + 1) & smask;
+    }
+    if (placed) {
+        float *t = tval + (uint64_t)slot * a.rank + r0;
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (r0 + j < a.rank) __hip_atomic_fetch_add(t + j, acc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+        global_add(a, row, r0, acc);
+    }
+}
+
+template <int LPN, typename FT, int WORDS>
+__global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    constexpr int SB = LPN < 4 ? LPN : 4;  // nonzeros gathered together
+    const int S = a.tile_merge ? (1 << a.slots_log2) : 0;
+    uint32_t *tkey = smem;
+    float *tval = (float *)(smem + S);
+    uint32_t *stage = smem + S + (size_t)S * a.rank;
+    const int REC = a.rec;
+    const int tid = threadIdx.x;
+    const int q = tid & (LPN - 1);
+    const int grp = tid / LPN;
+    const int ngrp = blockDim.x / LPN;
+    uint32_t *gst = stage + grp * LPN * REC;
+    const int r0 = 4 * q;
+    const bool ract = r0 < a.rank;
+    const int nother = a.nmodes - 1;
+
+    if (a.tile_merge) {
+        for (int i = tid; i < S; i += blockDim.x) tkey[i] = kEmptyRow;
+        for (int i = tid; i < S * a.rank; i += blockDim.x) tval[i] = 0.f;
+        __syncthreads();
+    }
+
+    // tiles of this workgroup
+    uint64_t t0, t1, tstep;
+    if (a.xcd_map) {
+        const uint32_t per = gridDim.x / 8, xcd = blockIdx.x % 8;
+        t0 = (a.ntiles * xcd) / 8 + blockIdx.x / 8;
+        t1 = (a.ntiles * (xcd + 1)) / 8;
+        tstep = per;
+    } else {
+        t0 = blockIdx.x;
+        t1 = a.ntiles;
+        tstep = gridDim.x;
+    }
+
+    for (uint64_t t = t0; t < t1; t += tstep) {
+        const uint64_t ts = t * a.tq + (t * a.tr) / a.ntiles;
+        const uint64_t te = (t + 1) * a.tq + ((t + 1) * a.tr) / a.ntiles;
+        const uint64_t per = (te - ts + ngrp - 1) / ngrp;
+        uint64_t ga = ts + (uint64_t)grp * per;
+        if (ga > te) ga = te;
+        const uint64_t gb = (ga + per < te) ? ga + per : te;
+
+        uint32_t cur = kEmptyRow;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+
+        for (uint64_t base = ga; base < gb; base += LPN) {
+            // ---- one index per lane: load, de-linearize, stage
+            const uint64_t x = base + q;
+            uint32_t *rec = gst + q * REC;
+            if (x < gb) {
+                const uint64_t lo = a.keys[x * WORDS];
+                const uint64_t hi = WORDS == 2 ? a.keys[x * WORDS + 1] : 0;
+                const uint32_t row = extract_mode<WORDS>(a.lp.mode[a.mode], lo, hi);
+                // indices decode from valid coordinates; the checks below only
+                // keep a corrupted index from reaching memory
+                const bool row_ok = row < a.dim_out;
+                rec[0] = row_ok ? __float_as_uint(a.vals[x]) : 0u;
+                rec[1] = row_ok ? row : kEmptyRow;
+                // modes in a rolled loop: each mode's masks are fetched into
+                // scalar registers when needed instead of all at once
+                int k = 2;
+#pragma unroll 1
+                for (int m = 0; m < a.nmodes; m++) {
+                    if (m != a.mode) {
+                        rec[k] = extract_mode<WORDS>(a.lp.mode[m], lo, hi);
+                        k++;
+                    }
+                }
+            } else {
+                rec[0] = 0u;
+                rec[1] = kEmptyRow;
+                for (int k = 2; k < 2 + nother; k++) rec[k] = 0u;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int cnt = (int)((gb - base) < (uint64_t)LPN ? (gb - base) : (uint64_t)LPN);
+
+            // ---- walk the batch in line order
+#pragma unroll
+            for (int sb = 0; sb < LPN; sb += SB) {
+                float p[SB][4];
+                uint32_t rows[SB];
+#pragma unroll
+                for (int s = 0; s < SB; s++) {
+                    const uint32_t *r = gst + (sb + s) * REC;
+                    const float v = __uint_as_float(r[0]);
+                    rows[s] = r[1];
+                    p[s][0] = v;
+                    p[s][1] = v;
+                    p[s][2] = v;
+                    p[s][3] = v;
+                }
+                for (int k = 0; k < nother; k++) {
+                    const void *f = a.fac_other[k];
+                    float4 g[SB];
+#pragma unroll
+                    for (int s = 0; s < SB; s++) {
+                        const uint32_t idx = min(gst[(sb + s) * REC + 2 + k], a.last_other[k]);
+                        g[s] = ract ? load4<FT>(f, (uint64_t)idx * a.rank + r0) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+#pragma unroll
+                    for (int s = 0; s < SB; s++) {
+                        p[s][0] *= g[s].x;
+                        p[s][1] *= g[s].y;
+                        p[s][2] *= g[s].z;
+                        p[s][3] *= g[s].w;
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < SB; s++) {
+                    if (sb + s < cnt) {
+                        if (rows[s] == cur) {
+#pragma unroll
+                            for (int j = 0; j < 4; j++) acc[j] += p[s][j];
+                        } else {
+                            if (cur != kEmptyRow) {
+                                if (a.tile_merge) table_add(a, tkey, tval, cur, r0, acc);
+                                else global_add(a, cur, r0, acc);
+                            }
+                            cur = rows[s];
+#pragma unroll
+                            for (int j = 0; j < 4; j++) acc[j] = p[s][j];
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (cur != kEmptyRow) {
+            if (a.tile_merge) table_add(a, tkey, tval, cur, r0, acc);
+            else global_add(a, cur, r0, acc);
+        }
+
+        if (a.tile_merge) {
+            // ---- add the tile's merged rows to the output, clear the table
+            __syncthreads();
+            const int qr = a.rank >> 2;
+            for (int i = tid; i < S * qr; i += blockDim.x) {
+                const int slot = i / qr, part = i - slot * qr;
+                const uint32_t row = tkey[slot];
+                if (row != kEmptyRow) {
+                    float *t = tval + (size_t)slot * a.rank + part * 4;
+                    const float4 v = *(const float4 *)t;
+                    const float vv[4] = {v.x, v.y, v.z, v.w};
+                    global_add(a, row, part * 4, vv);
+                    *(float4 *)t = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+            __syncthreads();
+            for (int i = tid; i < S; i += blockDim.x) tkey[i] = kEmptyRow;
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_round_f64(const double *__restrict__ in, float *__restrict__ out, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (float)in[i];
+}
+
+template <int LPN, typename FT, int WORDS>
+const void *kernel_ptr() {
+    return (const void *)k_mttkrp<LPN, FT, WORDS>;
+}
+
+
+template <typename FT, int WORDS>
+const void *pick_lpn(int lpn) {
+    switch (lpn) {
+        case 1: return kernel_ptr<1, FT, WORDS>();
+        case 2: return kernel_ptr<2, FT, WORDS>();
+        case 4: return kernel_ptr<4, FT, WORDS>();
+        case 8: return kernel_ptr<8, FT, WORDS>();
+        case 16: return kernel_ptr<16, FT, WORDS>();
+        default: return kernel_ptr<32, FT, WORDS>();
+    }
+}
+
+const void *pick_kernel(int lpn, int fdt, int words) {
+    if (fdt == ALTO_BF16) return words == 2 ? pick_lpn<uint16_t, 2>(lpn) : pick_lpn<uint16_t, 1>(lpn);
+    return words == 2 ? pick_lpn<float, 2>(lpn) : pick_lpn<float, 1>(lpn);
+}
+
+struct DevProps {
+    int cus = 0;
+};
+
+DevProps &props(int dev) {
+    static DevProps p[64];
+    if (dev >= 0 && dev < 64 && p[dev].cus == 0) {
+        hipDeviceProp_t dp;
+        if (hipGetDeviceProperties(&dp, dev) == hipSuccess) p[dev].cus = dp.multiProcessorCount;
+        else p[dev].cus = 256;
+    }
+    return p[dev < 0 || dev >= 64 ? 0 : dev];
+}
+
+}  // namespace
+
+int lpn_for(int rank) {
+    int l = 1;
+    while (4 * l < rank) l <<= 1;
+    return l;
+}
+
+alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt) {
+    alto_mttkrp_plan p;
+    memset(&p, 0, sizeof(p));
+    const double reuse = (double)h->info.nnz / (double)h->info.dims[mode];
+    // initial rule of the paper: buffered (tile) merging pays off when the
+    // average number of nonzeros per output fiber exceeds the 4 memory
+    // operations a buffered update costs in the worst case
+    p.conflict = reuse > 4.0 ? ALTO_CR_TILE : ALTO_CR_RUN;
+    p.block_threads = 256;
+    // LDS table of about 32 KiB of FP32 partial rows
+    int slots = 8192 / rank;
+    int s2 = 1;
+    while (s2 * 2 <= slots) s2 *= 2;
+    p.table_slots = std::max(64, s2);
+    p.tile_nnz = 4 * p.table_slots;
+    p.accumulate = ALTO_ACC_F64;
+    (void)fdt;
+    return p;
+}
+
+alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan *in,
+                         alto_mttkrp_plan *out) {
+    alto_mttkrp_plan p = default_plan(h, mode, rank, fdt);
+    const int ri = rank / 4;
+    if (ri >= 0 && ri <= 32 && h->has_tuned[mode][fdt][ri]) p = h->tuned[mode][fdt][ri];
+    if (in) {
+        if (in->conflict) p.conflict = in->conflict;
+        if (in->tile_nnz) p.tile_nnz = in->tile_nnz;
+        if (in->block_threads) p.block_threads = in->block_threads;
+        if (in->table_slots) p.table_slots = in->table_slots;
+        if (in->accumulate) p.accumulate = in->accumulate;
+    }
+    if (p.accumulate != ALTO_ACC_F64 && p.accumulate != ALTO_ACC_F32) return fail(ALTO_ERR_ARG, "bad accumulate mode");
+    if (p.conflict != ALTO_CR_TILE && p.conflict != ALTO_CR_RUN) return fail(ALTO_ERR_ARG, "bad conflict mode");
+    if (p.block_threads != 256) return fail(ALTO_ERR_ARG, "block_threads must be 256");
+    if (p.tile_nnz < 1) return fail(ALTO_ERR_ARG, "tile_nnz must be positive");
+    if (p.conflict == ALTO_CR_TILE) {
+        if (p.table_slots < 16 || (p.table_slots & (p.table_slots - 1)))
+            return fail(ALTO_ERR_ARG, "table_slots must be a power of two >= 16");
+        const size_t lds = (size_t)p.table_slots * (rank + 1) * 4;
+        if (lds > 96 * 1024) return fail(ALTO_ERR_ARG, "LDS table too large for rank");
+    }
+    *out = p;
+    return ALTO_OK;
+}
+
+alto_status check_mttkrp_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
+                              const float *out) {
+    ALTO_CHECK_HANDLE(h);
+    if (mode < 0 || mode >= h->info.nmodes) return fail(ALTO_ERR_ARG, "mode out of range");
+    if (rank < 4 || rank > ALTO_MAX_RANK || rank % 4) return fail(ALTO_ERR_ARG, "rank must be a multiple of 4 in 4..128");
+    if (fdt != ALTO_F32 && fdt != ALTO_BF16) return fail(ALTO_ERR_ARG, "bad factor dtype");
+    if (!out) return fail(ALTO_ERR_ARG, "out is NULL");
+    if (((uintptr_t)out & 15) != 0) return fail(ALTO_ERR_ARG, "out must be 16-byte aligned");
+    if (!factors) return fail(ALTO_ERR_ARG, "factors is NULL");
+    const uintptr_t al = fdt == ALTO_F32 ? 15 : 7;
+    for (int m = 0; m < h->info.nmodes; m++) {
+        if (m == mode) continue;
+        if (!factors[m]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(m) + "] is NULL");
+        if ((uintptr_t)factors[m] & al) return fail(ALTO_ERR_ARG, "factor rows must be 16-byte (8 for BF16) aligned");
+    }
+    return ALTO_OK;
+}
+
+alto_status ensure_ws(void **p, size_t *have, size_t need) {
+    if (*have >= need && *p) return ALTO_OK;
+    if (*p) {
+        ALTO_HIP(hipDeviceSynchronize());
+        dev_free(*p);
+        *p = nullptr;
+        *have = 0;
+    }
+    if (dev_alloc(p, need) != hipSuccess) return fail(ALTO_ERR_OOM, "workspace allocation failed");
+    *have = need;
+    return ALTO_OK;
+}
+
+void fill_args(const alto_tensor *h, int mode, int rank, const void *const *factors, const alto_mttkrp_plan &p,
+               float *out32, double *out64, MttkrpArgs *a) {
+    memset(a, 0, sizeof(*a));
+    a->lp = h->lp;
+    int k = 0;
+    for (int m = 0; m < h->info.nmodes; m++)
+        if (m != mode) {
+            a->last_other[k] = (uint32_t)(h->info.dims[m] - 1);
+            a->fac_other[k++] = factors[m];
+        }
+    a->dim_out = (uint32_t)h->info.dims[mode];
+    a->keys = h->keys;
+    a->vals = h->vals;
+    a->out32 = out32;
+    a->out64 = out64;
+    a->nnz = h->info.nnz;
+    uint64_t L = (h->info.nnz + p.tile_nnz - 1) / p.tile_nnz;
+    if (L < 1) L = 1;
+    a->ntiles = L;
+    a->tq = h->info.nnz / L;
+    a->tr = h->info.nnz % L;
+    a->mode = mode;
+    a->rank = rank;
+    a->nmodes = h->info.nmodes;
+    a->tile_merge = p.conflict == ALTO_CR_TILE ? 1 : 0;
+    a->use64 = p.accumulate == ALTO_ACC_F64 ? 1 : 0;
+    int l2 = 0;
+    while ((1 << l2) < p.table_slots) l2++;
+    a->slots_log2 = l2;
+    a->rec = ((h->info.nmodes + 1) + 3) / 4 * 4;
+}
+
+size_t lds_bytes(const MttkrpArgs &a, int threads) {
+    const size_t S = a.tile_merge ? ((size_t)1 << a.slots_log2) : 0;
+    return (S + S * a.rank) * 4 + (size_t)threads * a.rec * 4;
+}
+
+alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s) {
+    const int lpn = lpn_for(a.rank);
+    const void *kern = pick_kernel(lpn, fdt, h->info.index_words);
+    const size_t lds = lds_bytes(a, threads);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        occ = 1;
+    }
+    const int cus = props(h->device).cus;
+    uint64_t grid = (uint64_t)cus * occ;
+    MttkrpArgs b = a;
+    if (grid >= a.ntiles) {
+        grid = a.ntiles;
+        b.xcd_map = 0;
+    } else {
+        grid = grid / 8 * 8;
+        b.xcd_map = 1;
+    }
+    if (grid < 1) grid = 1;
+    void *args[] = {(void *)&b};
+    ALTO_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(threads), args, lds, s));
+    return ALTO_OK;
+}
+
+alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
+                       const alto_mttkrp_plan &p, hipStream_t s) {
+    const uint64_t nout = h->info.dims[mode] * (uint64_t)rank;
+    double *out64 = nullptr;
+    if (p.accumulate == ALTO_ACC_F64) {
+        alto_status st = ensure_ws(&h->ws_acc, &h->ws_acc_bytes, nout * 8);
+        if (st != ALTO_OK) return st;
+        out64 = (double *)h->ws_acc;
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(nout, 256, 16384)), dim3(256), 0, s, out64, nout, 0.0);
+    } else {
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(nout, 256, 16384)), dim3(256), 0, s, out, nout, 0.f);
+    }
+    ALTO_HIP(hipGetLastError());
+    if (h->info.nnz > 0) {
+        MttkrpArgs a;
+        fill_args(h, mode, rank, factors, p, out, out64, &a);
+        alto_status st = launch_mttkrp(h, fdt, a, p.block_threads, s);
+        if (st != ALTO_OK) return st;
+    }
+    if (p.accumulate == ALTO_ACC_F64) {
+        hipLaunchKernelGGL(k_round_f64, dim3(grid_for(nout, 256, 16384)), dim3(256), 0, s, out64, out, nout);
+        ALTO_HIP(hipGetLastError());
+    }
+    return ALTO_OK;
+}
+
+}  // namespace alto
+
+using namespace alto;
+
+extern "C" {
+
+alto_status alto_mttkrp_ex(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors, float *out,
+                           const alto_mttkrp_plan *plan, void *stream) {
+    alto_status st = check_mttkrp_args(h, mode, rank, fdt, factors, out);
+    if (st != ALTO_OK) return st;
+    alto_mttkrp_plan p;
+    st = resolve_plan(h, mode, rank, fdt, plan, &p);
+    if (st != ALTO_OK) return st;
+    return run_mttkrp(h, mode, rank, fdt, factors, out, p, (hipStream_t)stream);
+}
+
+alto_status alto_mttkrp(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors, float *out,
+                        void *stream) {
+    return alto_mttkrp_ex(h, mode, rank, fdt, factors, out, nullptr, stream);
+}
+
+alto_status alto_mttkrp_get_plan(alto_handle h, int mode, int rank, alto_dtype fdt, alto_mttkrp_plan *out) {
+    ALTO_CHECK_HANDLE(h);
+    if (!out) return fail(ALTO_ERR_ARG, "out is NULL");
+    if (mode < 0 || mode >= h->info.nmodes) return fail(ALTO_ERR_ARG, "mode out of range");
+    if (rank < 4 || rank > ALTO_MAX_RANK || rank % 4) return fail(ALTO_ERR_ARG, "rank must be a multiple of 4 in 4..128");
+    if (fdt != ALTO_F32 && fdt != ALTO_BF16) return fail(ALTO_ERR_ARG, "bad factor dtype");
+    return resolve_plan(h, mode, rank, fdt, nullptr, out);
+}
+
+}  // extern "C"

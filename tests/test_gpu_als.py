@@ -1,0 +1,115 @@
+"""GPU CP-ALS sweep parity with the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_cases import bf16_round, case, factors_for, rel_fro, say, upload, vals32
+from test_oracle_mttkrp import exact_low_rank
+
+pytestmark = pytest.mark.gpu
+
+alto = pytest.importorskip("paper_2403_06348_amd")
+torch = pytest.importorskip("torch")
+
+
+def oracle_mode_update(X, cur, n, quantize=False):
+    """One mode update of Algorithm "alg:cp-als" in FP64 from the factors the
+    GPU held when it updated mode n (Grams from FP32 masters; MTTKRP from the
+    BF16-rounded factors when ``quantize``)."""
+    v = vals32(X).astype(np.float64)
+    f64 = [c.astype(np.float64) for c in cur]
+    fm = [bf16_round(c).astype(np.float64) for c in cur] if quantize else f64
+    R = cur[0].shape[1]
+    V = np.ones((R, R))
+    for m in range(X.nmodes):
+        if m != n:
+            V *= f64[m].T @ f64[m]
+    M = oracle.mttkrp(X.dims, X.coords, v, fm, n)
+    An, ok = oracle._solve_spd_or_pinv(V, M)
+    lam = np.linalg.norm(An, axis=0)
+    return An / np.where(lam > 0, lam, 1.0), lam, ok, V, M
+
+
+@pytest.mark.parametrize("name,rank,fdt", [("c1", 8, "f32"), ("c2s", 16, "f32"), ("c3s", 32, "f32"),
+                                           ("c2s", 64, "bf16"), ("w128", 16, "f32")])
+def test_sweep_per_mode_parity(name, rank, fdt):
+    X = case(name)
+    coords, vals = upload(X)
+    T = alto.AltoTensor(X.dims, coords, vals)
+    facs = factors_for(X, rank, seed=21)
+    gf = [torch.from_numpy(f.copy()).cuda() for f in facs]
+    say(f"[als] sweep {name} R={rank} {fdt}")
+    lam = T.sweep(gf, fdt=alto.BF16 if fdt == "bf16" else alto.F32)
+    torch.cuda.synchronize()
+    assert T.sweep_flags() == 0
+    new = [g.cpu().numpy() for g in gf]
+    for n in range(X.nmodes):
+        cur = [new[m] if m < n else facs[m] for m in range(X.nmodes)]
+        ref, ref_lam, ok, V, M = oracle_mode_update(X, cur, n, quantize=(fdt == "bf16"))
+        assert ok
+        e = rel_fro(new[n].astype(np.float64), ref)
+        kappa = np.linalg.cond(V)
+        # forward error of A = M V^-1 for a right-hand side with relative
+        # error <= 1e-5 (the MTTKRP bound) is at most cond(V) * 1e-5
+        tol = max(1e-5, kappa * 1e-5)
+        say(f"    mode {n}: factor rel err {e:.3e}  cond(V) {kappa:.1f}  tol {tol:.1e}")
+        assert e <= tol, (n, e)
+        np.testing.assert_allclose(np.linalg.norm(new[n].astype(np.float64), axis=0), 1.0, rtol=1e-5)
+        if n == X.nmodes - 1:
+            got_lam = lam.cpu().numpy()
+            assert rel_fro(got_lam, ref_lam) <= tol
+            # backward error: the GPU's unnormalized update solves A V = M
+            # up to the MTTKRP error, whatever the conditioning of V
+            res = rel_fro(new[n].astype(np.float64) * got_lam @ V, M)
+            say(f"    mode {n}: normal-equation residual {res:.3e}")
+            assert res <= 1e-5
+    T.free()
+
+
+def test_sweep_matches_whole_oracle_sweep_small():
+    X = case("c1")
+    coords, vals = upload(X)
+    T = alto.AltoTensor(X.dims, coords, vals)
+    facs = factors_for(X, 8, seed=3)
+    gf = [torch.from_numpy(f.copy()).cuda() for f in facs]
+    say("[als] whole sweep c1")
+    lam = T.sweep(gf)
+    A, lam_ref, ok = oracle.als_sweep(X.dims, X.coords, vals32(X).astype(np.float64),
+                                      [f.astype(np.float64) for f in facs])
+    for n in range(3):
+        assert rel_fro(gf[n].cpu().numpy().astype(np.float64), A[n]) <= 1e-4
+    assert rel_fro(lam.cpu().numpy(), lam_ref) <= 1e-4
+    T.free()
+
+
+def test_sweep_fixed_point_exact_rank():
+    dims = (40, 50, 60)
+    facs, lam_true, coords, vals = exact_low_rank(dims, 8, seed=4)
+    T = alto.AltoTensor(dims, torch.from_numpy(coords).cuda(), torch.from_numpy(vals.astype(np.float32)).cuda())
+    gf = [torch.from_numpy(f.astype(np.float32)).cuda() for f in facs]
+    say("[als] fixed point")
+    lam = T.sweep(gf)
+    for n in range(3):
+        assert rel_fro(gf[n].cpu().numpy().astype(np.float64), facs[n]) <= 1e-5
+    assert rel_fro(lam.cpu().numpy(), lam_true) <= 1e-5
+    T.free()
+
+
+def test_sweep_pseudoinverse_fallback():
+    X = case("c1")
+    coords, vals = upload(X)
+    T = alto.AltoTensor(X.dims, coords, vals)
+    facs = factors_for(X, 8, seed=5)
+    for n in (1, 2):
+        facs[n][:, 3] = facs[n][:, 2]
+    gf = [torch.from_numpy(f.copy()).cuda() for f in facs]
+    say("[als] pseudo-inverse fallback")
+    T.sweep(gf)
+    flags = T.sweep_flags()
+    assert flags & 1
+    got0 = gf[0].cpu().numpy().astype(np.float64)
+    ref0, _, ok, _, _ = oracle_mode_update(X, facs, 0)
+    assert not ok
+    assert rel_fro(got0, ref0) <= 1e-4
+    T.free()

@@ -1,0 +1,109 @@
+"""GPU MTTKRP parity with the FP64 oracle: relative Frobenius error per mode
+<= 1e-5 for FP32 factors; BF16 factors are compared with the oracle run on
+the same BF16-rounded factors (accumulation error only)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_cases import bf16_round, case, factors_for, rel_fro, say, upload, vals32
+
+pytestmark = pytest.mark.gpu
+
+alto = pytest.importorskip("paper_2403_06348_amd")
+torch = pytest.importorskip("torch")
+
+TOL = 1e-5
+
+_built = {}
+
+
+def built(name):
+    if name not in _built:
+        X = case(name)
+        coords, vals = upload(X)
+        _built[name] = (X, alto.AltoTensor(X.dims, coords, vals))
+    return _built[name]
+
+
+def oracle_modes(X, facs):
+    v = vals32(X).astype(np.float64)
+    f64 = [f.astype(np.float64) for f in facs]
+    return [oracle.mttkrp(X.dims, X.coords, v, f64, n) for n in range(X.nmodes)]
+
+
+PLANS = {
+    "default": None,
+    "tile_f32": dict(conflict=alto.CR_TILE, accumulate=alto.ACC_F32),
+    "tile_f64_small": dict(conflict=alto.CR_TILE, accumulate=alto.ACC_F64, tile_nnz=1000, table_slots=64),
+    "run_f64": dict(conflict=alto.CR_RUN, accumulate=alto.ACC_F64),
+    "run_f32": dict(conflict=alto.CR_RUN, accumulate=alto.ACC_F32, tile_nnz=777),
+}
+
+
+@pytest.mark.parametrize("name,rank", [("c1", 8), ("c2s", 16), ("c3s", 32), ("w128", 12), ("unit", 20),
+                                       ("lowreuse", 16)])
+@pytest.mark.parametrize("plan", list(PLANS))
+def test_mttkrp_parity(name, rank, plan):
+    X, T = built(name)
+    facs = factors_for(X, rank)
+    refs = oracle_modes(X, facs)
+    gf = [torch.from_numpy(f).cuda() for f in facs]
+    for n in range(X.nmodes):
+        say(f"[mttkrp] {name} R={rank} plan={plan} mode={n}")
+        got = T.mttkrp(n, gf, plan=PLANS[plan]).cpu().numpy().astype(np.float64)
+        err = rel_fro(got, refs[n])
+        say(f"    rel err {err:.3e}")
+        assert err <= TOL, (n, err)
+
+
+@pytest.mark.parametrize("rank", [4, 8, 16, 24, 32, 64, 128])
+def test_mttkrp_ranks(rank):
+    X, T = built("c2s")
+    facs = factors_for(X, rank, seed=rank)
+    refs = oracle_modes(X, facs)
+    gf = [torch.from_numpy(f).cuda() for f in facs]
+    for n in range(X.nmodes):
+        say(f"[mttkrp] ranks R={rank} mode={n}")
+        got = T.mttkrp(n, gf).cpu().numpy().astype(np.float64)
+        assert rel_fro(got, refs[n]) <= TOL
+
+
+@pytest.mark.parametrize("name,rank", [("c2s", 16), ("c3s", 32), ("c2s", 64)])
+def test_mttkrp_bf16_factors(name, rank):
+    X, T = built(name)
+    facs = factors_for(X, rank)
+    rounded = [bf16_round(f) for f in facs]
+    refs_q = oracle_modes(X, rounded)
+    refs = oracle_modes(X, facs)
+    bf = [torch.from_numpy(f).cuda().to(torch.bfloat16).view(torch.int16) for f in facs]
+    for n in range(X.nmodes):
+        say(f"[mttkrp] bf16 {name} R={rank} mode={n}")
+        got = T.mttkrp(n, bf, rank=rank, fdt=alto.BF16).cpu().numpy().astype(np.float64)
+        e_acc = rel_fro(got, refs_q[n])
+        e_q = rel_fro(got, refs[n])
+        say(f"    vs oracle(bf16 factors) {e_acc:.3e}  vs oracle(fp32 factors) {e_q:.3e}")
+        assert e_acc <= TOL
+        # quantisation: each factor entry carries at most 2^-9 relative error
+        assert e_q <= (X.nmodes - 1) * 2.0**-8
+
+
+def test_mttkrp_argument_errors():
+    X, T = built("c1")
+    gf = [torch.rand(d, 8, device="cuda") for d in X.dims]
+    with pytest.raises(alto.AltoError):
+        T.mttkrp(3, gf)
+    with pytest.raises(alto.AltoError):
+        T.mttkrp(0, gf, rank=6)
+    with pytest.raises(alto.AltoError):
+        T.mttkrp(0, [gf[0], None, gf[2]])
+    with pytest.raises(alto.AltoError):
+        T.mttkrp(0, gf, plan=dict(table_slots=100, conflict=alto.CR_TILE))
+
+
+def test_repeat_runs_agree():
+    X, T = built("c2s")
+    facs = [torch.from_numpy(f).cuda() for f in factors_for(X, 16)]
+    a = T.mttkrp(0, facs).cpu().numpy()
+    b = T.mttkrp(0, facs).cpu().numpy()
+    assert rel_fro(a.astype(np.float64), b.astype(np.float64)) <= 1e-6
