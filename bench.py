@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Benchmark of the ALTO MTTKRP / CP-ALS hot path on one MI355X.
+
+Workload (default): 3-mode tensor 1e6 x 5e5 x 1e5 with 1e8 nonzeros whose
+coordinates follow Zipf(1.2) per mode over a shuffled index, U(0,1) FP32
+values, rank-16 FP32 factors (synthetic stand-in for the paper's FROSTT /
+HaTen2 tensors).  One step is the whole hot path on that input, resident in
+HBM: ALTO format generation (plan, linearize, radix sort), line partitioning
+with mode intervals, MTTKRP on every mode, and one CP-ALS sweep (which runs
+MTTKRP on every mode again, plus the FP64 R x R solves).
+
+Prints ONE JSON line.  `value` is MTTKRP nonzero-mode updates per second over
+whole steps (2 x nmodes MTTKRPs per step, format generation included).
+`roofline` rates the main MTTKRP kernel alone: algorithmic bytes per launch
+(index + value + the (N-1) gathered factor rows per nonzero, plus the output
+once) over its HIP-event-timed launch duration, against 8 TB/s HBM.
+`cpu_baseline` is the FP64 oracle (plain single-threaded C loop) timed on a
+bounded sample of the same tensor on this machine's host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MTTKRP GNNZ/s + % HBM roofline (R=16); served CP-ALS sweep p50/p99"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mttkrp_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2403_06348_amd", "csrc", "mttkrp.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(dims, nnz, rank, words, fbytes, mode):
+    """Bytes one MTTKRP launch must move by the paper's per-nonzero count:
+    index + value + (N-1) factor rows per nonzero, plus the output once."""
+    n = len(dims)
+    per_nz = 8 * words + 4 + (n - 1) * rank * fbytes
+    return nnz * per_nz + dims[mode] * rank * 4
+
+
+def traffic_for(workload: str):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    calibrated with a copy kernel) if recorded for the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = t.get(workload)
+    if not rec or rec.get("kernel_sha") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(X, rank, budget_nnz):
+    import numpy as np
+
+    import oracle
+    from synth import make_factors
+
+    m = min(budget_nnz, X.nnz)
+    coords = np.ascontiguousarray(X.coords[:, :m])
+    vals = X.vals[:m].astype(np.float64)
+    facs = [f.astype(np.float64) for f in make_factors(X.dims, rank, seed=7)]
+    t0 = time.perf_counter()
+    for n in range(X.nmodes):
+        oracle.mttkrp(X.dims, coords, vals, facs, n)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(m * X.nmodes / dt / 1e9, 6),
+        "unit": "GNNZ/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {m} of {X.nnz} nonzeros (generator order, a uniform sample), MTTKRP on all "
+        f"{X.nmodes} modes, FP64 single-threaded C loop, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4"])
+    ap.add_argument("--nnz", type=int, default=None, help="override nonzero count (smaller runs)")
+    ap.add_argument("--cpu-sample", type=int, default=40_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plan", default=None, help="JSON MTTKRP plan override")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2403_06348_amd as alto
+    from synth import CONFIGS, make_config, make_factors
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    spec = CONFIGS[args.config]
+    rank = spec["rank"]
+    fdt = alto.BF16 if spec.get("factor_dtype") == "bf16" else alto.F32
+    plan = json.loads(args.plan) if args.plan else None
+
+    t = time.perf_counter()
+    X = make_config(args.config, nnz=args.nnz)
+    log(f"[bench] generated {args.config}: dims={X.dims} nnz={X.nnz} in {time.perf_counter() - t:.1f}s")
+    coords = torch.from_numpy(X.coords).cuda()
+    vals = torch.from_numpy(np.ascontiguousarray(X.vals.astype(np.float32))).cuda()
+    facs0 = [torch.from_numpy(f).cuda() for f in make_factors(X.dims, rank, seed=7)]
+    work = [f.clone() for f in facs0]
+    outs = [torch.empty((d, rank), dtype=torch.float32, device="cuda") for d in X.dims]
+    lam = torch.empty(rank, dtype=torch.float64, device="cuda")
+    nseg = max(1, X.nnz // 4096)
+    starts = torch.empty(nseg + 1, dtype=torch.int64, device="cuda")
+    if fdt == alto.BF16:
+        mfacs = [f.to(torch.bfloat16).view(torch.int16) for f in facs0]
+    else:
+        mfacs = facs0
+
+    def step():
+        T = alto.AltoTensor(X.dims, coords, vals)  # plan, linearize, order
+        T.partition(nseg)  # balanced line segments + mode intervals
+        for n in range(X.nmodes):
+            T.mttkrp(n, mfacs, out=outs[n], rank=rank, fdt=fdt, plan=plan)
+        for w, f in zip(work, facs0):
+            w.copy_(f)
+        T.sweep(work, lam=lam, fdt=fdt)
+        T.free()
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup step {i} done")
+    torch.cuda.synchronize()
+    alto.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kms = alto.timing_read()
+    alto.timing_enable(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step")
+
+    info_words = alto.plan_dims(X.dims)["index_words"]
+    fbytes = 2 if fdt == alto.BF16 else 4
+    bytes_modes = [algorithmic_bytes(X.dims, X.nnz, rank, info_words, fbytes, n) for n in range(X.nmodes)]
+    mttkrp_per_step = 2 * X.nmodes
+    assert launches == mttkrp_per_step * args.steps, (launches, mttkrp_per_step * args.steps)
+    avg_launch_ms = kms / launches
+    avg_bytes = sum(bytes_modes) / X.nmodes
+    achieved = avg_bytes / (avg_launch_ms * 1e-3) / 1e9
+    value = X.nnz * mttkrp_per_step / (ms_per_step * 1e-3) / 1e9
+
+    # phase breakdown (outside the timed region)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    T = alto.AltoTensor(X.dims, coords, vals)
+    per_mode = []
+    for n in range(X.nmodes):
+        ev[0].record()
+        for _ in range(3):
+            T.mttkrp(n, mfacs, out=outs[n], rank=rank, fdt=fdt, plan=plan)
+        ev[1].record()
+        torch.cuda.synchronize()
+        per_mode.append(ev[0].elapsed_time(ev[1]) / 3)
+    for w, f in zip(work, facs0):
+        w.copy_(f)
+    ev[0].record()
+    T.sweep(work, lam=lam, fdt=fdt)
+    ev[1].record()
+    torch.cuda.synchronize()
+    sweep_ms = ev[0].elapsed_time(ev[1])
+    plans = [T.get_plan(n, rank, fdt) for n in range(X.nmodes)]
+    T.free()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    T = alto.AltoTensor(X.dims, coords, vals)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb) * 1e3
+    T.free()
+
+    workload = f"{args.config}" + (f"-nnz{X.nnz}" if args.nnz else "")
+    traffic = traffic_for(workload)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "GNNZ/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-factors/f32-accumulate" if fdt == alto.BF16 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": spec["desc"] + "; step = ALTO build + partition + MTTKRP on all modes + one CP-ALS sweep",
+            "name": workload,
+            "dims": list(X.dims),
+            "nnz": X.nnz,
+            "rank": rank,
+            "mttkrp_per_step": mttkrp_per_step,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_mttkrp (main MTTKRP kernel), average over all launches in the timed region",
+            "alg_bytes_per_launch": round(avg_bytes),
+            "avg_launch_ms": round(avg_launch_ms, 5),
+            "kernel_sha": kernel_hash(),
+        },
+        "breakdown": {
+            "build_ms": round(build_ms, 3),
+            "mttkrp_call_ms_per_mode": [round(x, 4) for x in per_mode],
+            "sweep_ms": round(sweep_ms, 3),
+            "mttkrp_only_gnnz_s": round(X.nnz * X.nmodes / (sum(per_mode) * 1e-3) / 1e9, 3),
+            "plans": plans,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(X, rank, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -232,6 +232,22 @@ alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *con
  */
 alto_status alto_sweep_flags(alto_handle h, void *stream, uint32_t *flags /*host*/);
 
+/* ---------------------------------------------------------------- timing */
+
+/*
+ * Kernel timing for measurement tools.  While enabled (on != 0), every launch
+ * of the main MTTKRP kernel (alto_mttkrp*, the sweeps and batched calls) is
+ * bracketed by a pair of HIP events recorded on its launch stream.
+ * alto_timing_read waits for the recorded events, returns the number of
+ * launches and the sum of their durations in milliseconds, and clears the
+ * record.  Enabling or disabling also clears it.
+ */
+alto_status alto_timing_enable(int on);
+alto_status alto_timing_read(uint64_t *launches /*host*/, double *total_ms /*host*/);
+
+/* Return every cached device block to the device (hipFree). */
+alto_status alto_release_cached_memory(void);
+
 /* ---------------------------------------------------------------- misc */
 
 /* Thread-local description of the last failure (never NULL). */

@@ -60,6 +60,23 @@ def version() -> str:
     return _capi.lib().alto_version().decode()
 
 
+def timing_enable(on: bool = True) -> None:
+    """Record HIP events around every main MTTKRP kernel launch."""
+    _check(_capi.lib().alto_timing_enable(1 if on else 0), "alto_timing_enable")
+
+
+def timing_read():
+    """(launches, total_ms) of the main MTTKRP kernel since the last read."""
+    n = ctypes.c_uint64()
+    ms = ctypes.c_double()
+    _check(_capi.lib().alto_timing_read(ctypes.byref(n), ctypes.byref(ms)), "alto_timing_read")
+    return int(n.value), float(ms.value)
+
+
+def release_cached_memory() -> None:
+    _check(_capi.lib().alto_release_cached_memory(), "alto_release_cached_memory")
+
+
 def plan_dims(dims) -> dict:
     """Bit layout of the ALTO index for ``dims`` (host only)."""
     info = _capi.Info()

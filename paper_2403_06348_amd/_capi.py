@@ -145,6 +145,9 @@ SIGNATURES = {
     "cpd_als_sweep": (I32, [P, I32, P, P, P]),
     "cpd_als_sweep_ex": (I32, [P, I32, I32, P, P, P]),
     "alto_sweep_flags": (I32, [P, P, ctypes.POINTER(ctypes.c_uint32)]),
+    "alto_timing_enable": (I32, [I32]),
+    "alto_timing_read": (I32, [ctypes.POINTER(U64), ctypes.POINTER(ctypes.c_double)]),
+    "alto_release_cached_memory": (I32, []),
     "alto_last_error": (ctypes.c_char_p, []),
     "alto_version": (ctypes.c_char_p, []),
 }

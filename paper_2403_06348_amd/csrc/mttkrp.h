@@ -40,5 +40,8 @@ void fill_args(const alto_tensor *h, int mode, int rank, const void *const *fact
                float *out32, double *out64, MttkrpArgs *a);
 size_t lds_bytes(const MttkrpArgs &a, int threads);
 int lpn_for(int rank);
+alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s);
+bool timing_begin(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1);
+void timing_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 }  // namespace alto

@@ -27,7 +27,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "alto_internal.h"
 #include "device_util.h"
@@ -419,6 +421,59 @@ size_t lds_bytes(const MttkrpArgs &a, int threads) {
     return (S + S * a.rank) * 4 + (size_t)threads * a.rec * 4;
 }
 
+// ---- optional per-launch timing with HIP events
+namespace {
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<hipEvent_t> pool;
+};
+Timing &timing() {
+    static Timing *t = new Timing();
+    return *t;
+}
+hipEvent_t take_event(Timing &t) {
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+void clear_pending(Timing &t) {
+    for (auto &pr : t.pending) {
+        (void)hipEventSynchronize(pr.second);
+        t.pool.push_back(pr.first);
+        t.pool.push_back(pr.second);
+    }
+    t.pending.clear();
+}
+}  // namespace
+
+bool timing_begin(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1) {
+    Timing &t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.on) return false;
+    *e0 = take_event(t);
+    *e1 = take_event(t);
+    if (!*e0 || !*e1) return false;
+    (void)hipEventRecord(*e0, s);
+    return true;
+}
+
+void timing_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    Timing &t = timing();
+    (void)hipEventRecord(e1, s);
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.pending.push_back({e0, e1});
+}
+
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s) {
     const int lpn = lpn_for(a.rank);
     const void *kern = pick_kernel(lpn, fdt, h->info.index_words);
@@ -440,7 +495,10 @@ alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, in
     }
     if (grid < 1) grid = 1;
     void *args[] = {(void *)&b};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = timing_begin(s, &e0, &e1);
     ALTO_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(threads), args, lds, s));
+    if (timed) timing_end(s, e0, e1);
     return ALTO_OK;
 }
 
@@ -489,6 +547,37 @@ alto_status alto_mttkrp_ex(alto_handle h, int mode, int rank, alto_dtype fdt, co
 alto_status alto_mttkrp(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors, float *out,
                         void *stream) {
     return alto_mttkrp_ex(h, mode, rank, fdt, factors, out, nullptr, stream);
+}
+
+alto_status alto_timing_enable(int on) {
+    Timing &t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    clear_pending(t);
+    t.on = on != 0;
+    return ALTO_OK;
+}
+
+alto_status alto_timing_read(uint64_t *launches, double *total_ms) {
+    if (!launches || !total_ms) return fail(ALTO_ERR_ARG, "NULL argument");
+    Timing &t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    double tot = 0.0;
+    for (auto &pr : t.pending) {
+        float ms = 0.f;
+        ALTO_HIP(hipEventSynchronize(pr.second));
+        ALTO_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+    }
+    *launches = t.pending.size();
+    *total_ms = tot;
+    clear_pending(t);
+    return ALTO_OK;
+}
+
+alto_status alto_release_cached_memory(void) {
+    ALTO_HIP(hipDeviceSynchronize());
+    release_cached();
+    return ALTO_OK;
 }
 
 alto_status alto_mttkrp_get_plan(alto_handle h, int mode, int rank, alto_dtype fdt, alto_mttkrp_plan *out) {
