@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=40_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default=None, help="JSON MTTKRP plan override")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -148,6 +149,14 @@ def main():
         T.sweep(work, lam=lam, fdt=fdt)
         T.free()
 
+    if not args.no_autotune and plan is None:
+        # first sight of this tensor class: the library's autotuner picks a
+        # plan per mode and caches it for every later handle of the class
+        T = alto.AltoTensor(X.dims, coords, vals)
+        for n in range(X.nmodes):
+            p = T.autotune(n, mfacs, out=outs[n], rank=rank, fdt=fdt)
+            log(f"[bench] autotuned mode {n}: {p}")
+        T.free()
     for i in range(args.warmup):
         step()
         log(f"[bench] warmup step {i} done")

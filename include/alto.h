@@ -24,7 +24,7 @@
  *   - Every call returns an alto_status; on failure alto_last_error()
  *     (thread-local) describes it.  Argument errors are detected on the
  *     host before anything is enqueued.
- *   - Limits: 1 <= nmodes <= ALTO_MAX_MODES; 1 <= dims[n] < 2^32; the
+ *   - Limits: 1 <= nmodes <= ALTO_MAX_MODES; 1 <= dims[n] <= 2^31; the
  *     index width sum_n ceil(log2 dims[n]) <= 128 bits; nnz < 2^40;
  *     rank a multiple of 4 in 4..ALTO_MAX_RANK.
  */
@@ -69,8 +69,17 @@ typedef enum { ALTO_CR_AUTO = 0, ALTO_CR_TILE = 1, ALTO_CR_RUN = 2 } alto_confli
 
 /* Where the merged output rows are summed.
  * ALTO_ACC_F64: in an FP64 buffer (handle workspace), rounded once to FP32.
- * ALTO_ACC_F32: directly in the FP32 output with FP32 atomics. */
-typedef enum { ALTO_ACC_DEFAULT = 0, ALTO_ACC_F64 = 1, ALTO_ACC_F32 = 2 } alto_accumulate;
+ * ALTO_ACC_F32: directly in the FP32 output with FP32 atomics.
+ * ALTO_ACC_XCD_F32 / ALTO_ACC_XCD_F64: in one private FP32 / FP64 copy of the
+ *   output per XCD (the chiplet a workgroup runs on), summed in FP64 and
+ *   rounded once to FP32 at the end; atomics of different XCDs never meet. */
+typedef enum {
+    ALTO_ACC_DEFAULT = 0,
+    ALTO_ACC_F64 = 1,
+    ALTO_ACC_F32 = 2,
+    ALTO_ACC_XCD_F32 = 3,
+    ALTO_ACC_XCD_F64 = 4
+} alto_accumulate;
 
 /* Tunable launch plan of one MTTKRP.  Zero fields take the library default
  * (or the autotuned value when one was recorded for the handle and mode). */

@@ -36,6 +36,8 @@ CR_RUN = 2
 ACC_DEFAULT = 0
 ACC_F64 = 1
 ACC_F32 = 2
+ACC_XCD_F32 = 3
+ACC_XCD_F64 = 4
 
 
 class MttkrpPlan(ctypes.Structure):

@@ -37,15 +37,14 @@ struct LinePlan {
     int words;
 };
 
+// All six steps run unconditionally: a zero move mask makes a step a no-op,
+// and a branch per step would cost more scalar work than the step itself.
 __host__ __device__ inline uint64_t compress_word(uint64_t x, const WordMasks &m) {
     x &= m.mask;
 #pragma unroll
     for (int i = 0; i < 6; i++) {
-        const uint64_t mv = m.mv[i];
-        if (mv) {
-            const uint64_t t = x & mv;
-            x = (x ^ t) | (t >> (1u << i));
-        }
+        const uint64_t t = x & m.mv[i];
+        x = (x ^ t) | (t >> (1u << i));
     }
     return x;
 }

@@ -6,13 +6,18 @@
 
 namespace alto {
 
-constexpr int kMaxProbe = 16;  // LDS table probes before falling back to the output
+constexpr int kMaxProbe = 16;       // LDS table probes before falling back to the output
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr uint32_t kHotHits = 4;    // runs merged in one tile that make a row stay in LDS
+constexpr int kKeepTiles = 16;      // tiles a row may stay in LDS before it is flushed
 
 struct MttkrpArgs {
     LinePlan lp;
     const void *fac_other[ALTO_MAX_MODES];  // factors of the other modes, ascending mode order
     uint32_t last_other[ALTO_MAX_MODES];    // dims - 1 of those modes (gather index clamp)
     uint32_t dim_out;                       // dims[mode]
+    uint32_t fac_bytes[ALTO_MAX_MODES];     // byte size of those factors (buffer range)
+    int buf32;                              // 1: gathers through 32-bit buffer offsets
     const uint64_t *keys;
     const float *vals;
     float *out32;
@@ -26,9 +31,14 @@ struct MttkrpArgs {
     int slots_log2;
     int rec;          // staged record length (u32) per nonzero
     int xcd_map;      // 1: contiguous tile ranges per XCD
+    int copies;       // private output copies, indexed by XCD id (1: shared output)
+    uint64_t copy_stride;  // elements per copy
 };
 
+constexpr int kXcdCopies = 8;  // XCDs of an MI355X
+
 alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt);
+void record_tuned(alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan &p);
 alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan *in,
                          alto_mttkrp_plan *out);
 alto_status check_mttkrp_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
@@ -36,8 +46,8 @@ alto_status check_mttkrp_args(const alto_tensor *h, int mode, int rank, int fdt,
 alto_status ensure_ws(void **p, size_t *have, size_t need);
 alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
                        const alto_mttkrp_plan &p, hipStream_t s);
-void fill_args(const alto_tensor *h, int mode, int rank, const void *const *factors, const alto_mttkrp_plan &p,
-               float *out32, double *out64, MttkrpArgs *a);
+void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
+               const alto_mttkrp_plan &p, float *out32, double *out64, MttkrpArgs *a);
 size_t lds_bytes(const MttkrpArgs &a, int threads);
 int lpn_for(int rank);
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s);

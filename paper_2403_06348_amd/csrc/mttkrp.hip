@@ -27,6 +27,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <cmath>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -50,19 +53,50 @@ __device__ inline float4 load4<float>(const void *base, uint64_t elem) {
     return *(const float4 *)((const float *)base + elem);
 }
 
-template <>
-__device__ inline float4 load4<uint16_t>(const void *base, uint64_t elem) {
-    const uint2 u = *(const uint2 *)((const uint16_t *)base + elem);
+__device__ inline float4 bf16x4_to_float4(uint32_t lo, uint32_t hi) {
     float4 f;
-    f.x = __uint_as_float(u.x << 16);
-    f.y = __uint_as_float(u.x & 0xFFFF0000u);
-    f.z = __uint_as_float(u.y << 16);
-    f.w = __uint_as_float(u.y & 0xFFFF0000u);
+    f.x = __uint_as_float(lo << 16);
+    f.y = __uint_as_float(lo & 0xFFFF0000u);
+    f.z = __uint_as_float(hi << 16);
+    f.w = __uint_as_float(hi & 0xFFFF0000u);
     return f;
 }
 
+template <>
+__device__ inline float4 load4<uint16_t>(const void *base, uint64_t elem) {
+    const uint2 u = *(const uint2 *)((const uint16_t *)base + elem);
+    return bf16x4_to_float4(u.x, u.y);
+}
+
+// Factor-row gathers through a buffer resource: 32-bit byte offsets, and a
+// read past the end of the factor returns zeros instead of faulting.
+constexpr int kBufferFlags = 0x00020000;  // raw buffer, gfx9 family
+
+__device__ inline __amdgpu_buffer_rsrc_t factor_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferFlags);
+}
+
+template <typename FT>
+__device__ inline float4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t byte_off);
+
+template <>
+__device__ inline float4 bload4<float>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0);
+    return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+}
+
+template <>
+__device__ inline float4 bload4<uint16_t>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0);
+    return bf16x4_to_float4(v[0], v[1]);
+}
+
+// Hardware id of the XCD (accelerator complex die) running this wave.
+__device__ inline uint32_t xcd_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 15u; }
+
 __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, const float *acc) {
-    const uint64_t o = (uint64_t)row * a.rank + r0;
+    uint64_t o = (uint64_t)row * a.rank + r0;
+    if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
     if (a.use64) {
 #pragma unroll
         for (int j = 0; j < 4; j++)
@@ -74,41 +108,78 @@ __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, con
     }
 }
 
-// Merge a finished run of updates of `row` into the LDS table (or, when the
-// table has no room within the probe limit, into the output directly).
-__device__ inline void table_add(const MttkrpArgs &a, uint32_t *tkey, float *tval, uint32_t row, int r0,
-                                 const float *acc) {
-    const int log2s = a.slots_log2;
-    const uint32_t smask = (1u << log2s) - 1;
-    uint32_t slot = row_hash(row, log2s);
-    bool placed = false;
-    for (int probe = 0; probe < kMaxProbe; probe++) {
-        const uint32_t old = atomicCAS(tkey + slot, kEmptyRow, row);
-        if (old == kEmptyRow || old == row) {
-            placed = true;
-            break;
+// Slot of `row` in the LDS table of partial rows, inserting it if absent.
+// The table is bucketized: a row may live in one of the 4 slots of its
+// bucket (read with a single 16-byte LDS load) or of a second bucket, so a
+// lookup costs one or two LDS reads and never a long probe sequence.
+// kNoSlot when both buckets are full: the caller then adds to the output
+// directly.  A row may own two slots (after an eviction broke its lookup);
+// both are added to the output, so this only costs merging, never
+// correctness.
+__device__ inline uint32_t table_slot(uint32_t *tkey, uint32_t row, int log2s) {
+    const uint32_t bmask = (1u << (log2s - 2)) - 1;
+    const uint32_t b1 = row_hash(row, log2s - 2) & bmask;
+    const uint32_t b2 = (row_hash(row ^ 0x5bd1e995u, log2s - 2) ^ 1u) & bmask;
+#pragma unroll
+    for (int pass = 0; pass < 2; pass++) {
+        const uint32_t b = pass == 0 ? b1 : b2;
+        uint32_t *bk = tkey + 4 * b;
+        uint4 k4 = *(const uint4 *)bk;
+        const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (kk[j] == row) return 4 * b + j;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (kk[j] == kEmptyRow) {
+                const uint32_t old = atomicCAS(bk + j, kEmptyRow, row);
+                if (old == kEmptyRow || old == row) return 4 * b + j;
+            }
         }
-        slot = (slot + 1) & smask;
     }
-    if (placed) {
+    return kNoSlot;
+}
+
+// Destination of a nonzero's update, packed in one word: kSlotBit | slot for
+// an LDS slot, else the output row itself (rows are below 2^31).
+constexpr uint32_t kSlotBit = 0x80000000u;
+
+// Add a finished run of updates to its destination.
+__device__ inline void flush_run(const MttkrpArgs &a, float *tval, uint32_t *thits, uint32_t dst, int q, int r0,
+                                 const float *acc) {
+    if (dst & kSlotBit) {
+        const uint32_t slot = dst & ~kSlotBit;
         float *t = tval + (uint64_t)slot * a.rank + r0;
 #pragma unroll
         for (int j = 0; j < 4; j++)
             if (r0 + j < a.rank) __hip_atomic_fetch_add(t + j, acc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (q == 0) __hip_atomic_fetch_add(thits + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
-        global_add(a, row, r0, acc);
+        global_add(a, dst, r0, acc);
     }
 }
 
-template <int LPN, typename FT, int WORDS>
+constexpr uint32_t kFlushMark = 0xFFFFFFFFu;
+
+// Coordinate k of the other modes from a staged record held as two uint4.
+__device__ inline uint32_t rec_coord(const uint4 &h, const uint4 &h2, int k) {
+    return k == 0 ? h.z : k == 1 ? h.w : k == 2 ? h2.x : k == 3 ? h2.y : k == 4 ? h2.z : h2.w;
+}
+
+// Kernel variants: MAXO = most other modes handled with fully unrolled
+// gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
+template <int LPN, typename FT, int WORDS, int MAXO>
 __global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
-    constexpr int SB = LPN < 4 ? LPN : 4;  // nonzeros gathered together
+    __shared__ uint32_t nkeep;
+    // nonzeros gathered together per group
+    constexpr int SB = MAXO == 2 ? (LPN < 4 ? LPN : 4) : (LPN < 2 ? LPN : 2);
     const int S = a.tile_merge ? (1 << a.slots_log2) : 0;
     uint32_t *tkey = smem;
-    float *tval = (float *)(smem + S);
-    uint32_t *stage = smem + S + (size_t)S * a.rank;
-    const int REC = a.rec;
+    uint32_t *thits = smem + S;
+    float *tval = (float *)(smem + 2 * S);
+    uint32_t *stage = smem + 2 * S + (size_t)S * a.rank;
+    const int REC = a.rec;  // [val, destination, other coordinates...], multiple of 4
     const int tid = threadIdx.x;
     const int q = tid & (LPN - 1);
     const int grp = tid / LPN;
@@ -119,25 +190,23 @@ __global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
     const int nother = a.nmodes - 1;
 
     if (a.tile_merge) {
-        for (int i = tid; i < S; i += blockDim.x) tkey[i] = kEmptyRow;
+        for (int i = tid; i < S; i += blockDim.x) {
+            tkey[i] = kEmptyRow;
+            thits[i] = 0;
+        }
         for (int i = tid; i < S * a.rank; i += blockDim.x) tval[i] = 0.f;
         __syncthreads();
     }
 
-    // tiles of this workgroup
-    uint64_t t0, t1, tstep;
-    if (a.xcd_map) {
-        const uint32_t per = gridDim.x / 8, xcd = blockIdx.x % 8;
-        t0 = (a.ntiles * xcd) / 8 + blockIdx.x / 8;
-        t1 = (a.ntiles * (xcd + 1)) / 8;
-        tstep = per;
-    } else {
-        t0 = blockIdx.x;
-        t1 = a.ntiles;
-        tstep = gridDim.x;
-    }
+    // Each workgroup owns one contiguous stretch of tiles (a line segment
+    // in the paper's sense); the stretches of the workgroups that share an
+    // XCD are neighbours on the line, so they share factor rows in its L2.
+    const uint32_t G = gridDim.x;
+    const uint32_t rr = a.xcd_map ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+    const uint64_t t0 = (a.ntiles * rr) / G;
+    const uint64_t t1 = (a.ntiles * (rr + 1)) / G;
 
-    for (uint64_t t = t0; t < t1; t += tstep) {
+    for (uint64_t t = t0; t < t1; t++) {
         const uint64_t ts = t * a.tq + (t * a.tr) / a.ntiles;
         const uint64_t te = (t + 1) * a.tq + ((t + 1) * a.tr) / a.ntiles;
         const uint64_t per = (te - ts + ngrp - 1) / ngrp;
@@ -148,27 +217,65 @@ __global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
         uint32_t cur = kEmptyRow;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
 
+        // index and value of this lane's next nonzero, loaded one batch ahead
+        uint64_t nlo = 0, nhi = 0;
+        float nval = 0.f;
+        if (ga + q < gb) {
+            nlo = a.keys[(ga + q) * WORDS];
+            if (WORDS == 2) nhi = a.keys[(ga + q) * WORDS + 1];
+            nval = a.vals[ga + q];
+        }
         for (uint64_t base = ga; base < gb; base += LPN) {
-            // ---- one index per lane: load, de-linearize, stage
             const uint64_t x = base + q;
+            const uint64_t lo = nlo, hi = nhi;
+            const float val = nval;
+            if (x + LPN < gb) {
+                nlo = a.keys[(x + LPN) * WORDS];
+                if (WORDS == 2) nhi = a.keys[(x + LPN) * WORDS + 1];
+                nval = a.vals[x + LPN];
+            }
+            // ---- one nonzero per lane: de-linearize, find its LDS slot, stage
             uint32_t *rec = gst + q * REC;
             if (x < gb) {
-                const uint64_t lo = a.keys[x * WORDS];
-                const uint64_t hi = WORDS == 2 ? a.keys[x * WORDS + 1] : 0;
-                const uint32_t row = extract_mode<WORDS>(a.lp.mode[a.mode], lo, hi);
+                uint32_t c3[3] = {0u, 0u, 0u};
+                uint32_t row;
+                if (MAXO == 2 && WORDS == 1) {
+#pragma unroll
+                    for (int m = 0; m < 3; m++)
+                        if (m < a.nmodes) c3[m] = extract_mode<1>(a.lp.mode[m], lo, hi);
+                    row = a.mode == 0 ? c3[0] : (a.mode == 1 ? c3[1] : c3[2]);
+                } else {
+                    row = extract_mode<WORDS>(a.lp.mode[a.mode], lo, hi);
+                }
                 // indices decode from valid coordinates; the checks below only
                 // keep a corrupted index from reaching memory
                 const bool row_ok = row < a.dim_out;
-                rec[0] = row_ok ? __float_as_uint(a.vals[x]) : 0u;
-                rec[1] = row_ok ? row : kEmptyRow;
-                // modes in a rolled loop: each mode's masks are fetched into
-                // scalar registers when needed instead of all at once
-                int k = 2;
+                uint32_t dst = kEmptyRow;
+                if (row_ok) {
+                    dst = row;
+                    if (a.tile_merge) {
+                        const uint32_t slot = table_slot(tkey, row, a.slots_log2);
+                        if (slot != kNoSlot) dst = kSlotBit | slot;
+                    }
+                }
+                rec[0] = row_ok ? __float_as_uint(val) : 0u;
+                rec[1] = dst;
+                if (MAXO == 2 && WORDS == 1) {
+                    // up to 3 modes: the masks stay in scalar registers
+                    const uint32_t o0 = a.mode == 0 ? c3[1] : c3[0];
+                    const uint32_t o1 = a.mode == 2 ? c3[1] : c3[2];
+                    rec[2] = o0;
+                    rec[3] = o1;
+                } else {
+                    // modes in a rolled loop: each mode's masks are fetched
+                    // into scalar registers when needed instead of all at once
+                    int k = 2;
 #pragma unroll 1
-                for (int m = 0; m < a.nmodes; m++) {
-                    if (m != a.mode) {
-                        rec[k] = extract_mode<WORDS>(a.lp.mode[m], lo, hi);
-                        k++;
+                    for (int m = 0; m < a.nmodes; m++) {
+                        if (m != a.mode) {
+                            rec[k] = extract_mode<WORDS>(a.lp.mode[m], lo, hi);
+                            k++;
+                        }
                     }
                 }
             } else {
@@ -183,45 +290,80 @@ __global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
 #pragma unroll
             for (int sb = 0; sb < LPN; sb += SB) {
                 float p[SB][4];
-                uint32_t rows[SB];
+                uint4 head[SB], head2[SB];
 #pragma unroll
                 for (int s = 0; s < SB; s++) {
-                    const uint32_t *r = gst + (sb + s) * REC;
-                    const float v = __uint_as_float(r[0]);
-                    rows[s] = r[1];
+                    head[s] = *(const uint4 *)(gst + (sb + s) * REC);
+                    head2[s] = (MAXO > 2 && nother > 2) ? *(const uint4 *)(gst + (sb + s) * REC + 4)
+                                                        : make_uint4(0, 0, 0, 0);
+                    const float v = __uint_as_float(head[s].x);
                     p[s][0] = v;
                     p[s][1] = v;
                     p[s][2] = v;
                     p[s][3] = v;
                 }
-                for (int k = 0; k < nother; k++) {
-                    const void *f = a.fac_other[k];
-                    float4 g[SB];
+                if (MAXO <= 4) {
+                    // every gather of the batch is issued before the first
+                    // product is formed
+                    float4 g[MAXO][SB];
 #pragma unroll
-                    for (int s = 0; s < SB; s++) {
-                        const uint32_t idx = min(gst[(sb + s) * REC + 2 + k], a.last_other[k]);
-                        g[s] = ract ? load4<FT>(f, (uint64_t)idx * a.rank + r0) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    for (int k = 0; k < MAXO; k++) {
+                        if (k < nother) {
+                            if (a.buf32) {
+                                const __amdgpu_buffer_rsrc_t rs = factor_rsrc(a.fac_other[k], a.fac_bytes[k]);
+#pragma unroll
+                                for (int s = 0; s < SB; s++) {
+                                    const uint32_t idx = rec_coord(head[s], head2[s], k);
+                                    g[k][s] = bload4<FT>(rs, (idx * (uint32_t)a.rank + (uint32_t)r0) * (uint32_t)sizeof(FT));
+                                }
+                            } else {
+                                const void *f = a.fac_other[k];
+#pragma unroll
+                                for (int s = 0; s < SB; s++) {
+                                    const uint32_t idx = min(rec_coord(head[s], head2[s], k), a.last_other[k]);
+                                    g[k][s] = ract ? load4<FT>(f, (uint64_t)idx * a.rank + r0)
+                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+                                }
+                            }
+                        }
                     }
 #pragma unroll
-                    for (int s = 0; s < SB; s++) {
-                        p[s][0] *= g[s].x;
-                        p[s][1] *= g[s].y;
-                        p[s][2] *= g[s].z;
-                        p[s][3] *= g[s].w;
+                    for (int k = 0; k < MAXO; k++) {
+                        if (k < nother) {
+#pragma unroll
+                            for (int s = 0; s < SB; s++) {
+                                p[s][0] *= g[k][s].x;
+                                p[s][1] *= g[k][s].y;
+                                p[s][2] *= g[k][s].z;
+                                p[s][3] *= g[k][s].w;
+                            }
+                        }
+                    }
+                } else {
+                    for (int k = 0; k < nother; k++) {
+                        const void *f = a.fac_other[k];
+#pragma unroll
+                        for (int s = 0; s < SB; s++) {
+                            const uint32_t idx = min(gst[(sb + s) * REC + 2 + k], a.last_other[k]);
+                            const float4 g = ract ? load4<FT>(f, (uint64_t)idx * a.rank + r0)
+                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+                            p[s][0] *= g.x;
+                            p[s][1] *= g.y;
+                            p[s][2] *= g.z;
+                            p[s][3] *= g.w;
+                        }
                     }
                 }
 #pragma unroll
                 for (int s = 0; s < SB; s++) {
                     if (sb + s < cnt) {
-                        if (rows[s] == cur) {
+                        const uint32_t dst = head[s].y;
+                        if (dst == cur) {
 #pragma unroll
                             for (int j = 0; j < 4; j++) acc[j] += p[s][j];
                         } else {
-                            if (cur != kEmptyRow) {
-                                if (a.tile_merge) table_add(a, tkey, tval, cur, r0, acc);
-                                else global_add(a, cur, r0, acc);
-                            }
-                            cur = rows[s];
+                            if (cur != kEmptyRow) flush_run(a, tval, thits, cur, q, r0, acc);
+                            cur = dst;
 #pragma unroll
                             for (int j = 0; j < 4; j++) acc[j] = p[s][j];
                         }
@@ -230,59 +372,81 @@ __global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
             }
             __builtin_amdgcn_wave_barrier();
         }
-        if (cur != kEmptyRow) {
-            if (a.tile_merge) table_add(a, tkey, tval, cur, r0, acc);
-            else global_add(a, cur, r0, acc);
-        }
+        if (cur != kEmptyRow) flush_run(a, tval, thits, cur, q, r0, acc);
 
         if (a.tile_merge) {
-            // ---- add the tile's merged rows to the output, clear the table
+            // ---- tile end: rows merged many times in this tile (high reuse)
+            // stay in LDS for the next tile; the others are added to the
+            // output and their slots cleared.  Everything is flushed every
+            // kKeepTiles tiles and at the end of the workgroup's stretch.
+            __syncthreads();
+            const bool flush_all = (t + 1 == t1) || ((t - t0 + 1) % kKeepTiles == 0);
+            if (tid == 0) nkeep = 0;
+            __syncthreads();
+            for (int i = tid; i < S; i += blockDim.x) {
+                if (tkey[i] == kEmptyRow) continue;
+                bool keep = false;
+                if (!flush_all && thits[i] >= kHotHits) keep = atomicAdd(&nkeep, 1u) < (uint32_t)(S / 4);
+                thits[i] = keep ? 0u : kFlushMark;
+            }
             __syncthreads();
             const int qr = a.rank >> 2;
             for (int i = tid; i < S * qr; i += blockDim.x) {
                 const int slot = i / qr, part = i - slot * qr;
-                const uint32_t row = tkey[slot];
-                if (row != kEmptyRow) {
-                    float *t = tval + (size_t)slot * a.rank + part * 4;
-                    const float4 v = *(const float4 *)t;
+                if (thits[slot] == kFlushMark) {
+                    float *tv = tval + (size_t)slot * a.rank + part * 4;
+                    const float4 v = *(const float4 *)tv;
                     const float vv[4] = {v.x, v.y, v.z, v.w};
-                    global_add(a, row, part * 4, vv);
-                    *(float4 *)t = make_float4(0.f, 0.f, 0.f, 0.f);
+                    global_add(a, tkey[slot], part * 4, vv);
+                    *(float4 *)tv = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
             __syncthreads();
-            for (int i = tid; i < S; i += blockDim.x) tkey[i] = kEmptyRow;
+            for (int i = tid; i < S; i += blockDim.x) {
+                if (thits[i] == kFlushMark) {
+                    tkey[i] = kEmptyRow;
+                    thits[i] = 0;
+                }
+            }
             __syncthreads();
         }
     }
 }
 
-__global__ void k_round_f64(const double *__restrict__ in, float *__restrict__ out, uint64_t n) {
+// out = FP32 rounding of the FP64 sum over `copies` partial outputs.
+template <typename T>
+__global__ void k_sum_copies(const T *__restrict__ in, int copies, uint64_t n, float *__restrict__ out) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (float)in[i];
-}
-
-template <int LPN, typename FT, int WORDS>
-const void *kernel_ptr() {
-    return (const void *)k_mttkrp<LPN, FT, WORDS>;
-}
-
-
-template <typename FT, int WORDS>
-const void *pick_lpn(int lpn) {
-    switch (lpn) {
-        case 1: return kernel_ptr<1, FT, WORDS>();
-        case 2: return kernel_ptr<2, FT, WORDS>();
-        case 4: return kernel_ptr<4, FT, WORDS>();
-        case 8: return kernel_ptr<8, FT, WORDS>();
-        case 16: return kernel_ptr<16, FT, WORDS>();
-        default: return kernel_ptr<32, FT, WORDS>();
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double s = 0.0;
+        for (int c = 0; c < copies; c++) s += (double)in[(uint64_t)c * n + i];
+        out[i] = (float)s;
     }
 }
 
-const void *pick_kernel(int lpn, int fdt, int words) {
-    if (fdt == ALTO_BF16) return words == 2 ? pick_lpn<uint16_t, 2>(lpn) : pick_lpn<uint16_t, 1>(lpn);
-    return words == 2 ? pick_lpn<float, 2>(lpn) : pick_lpn<float, 1>(lpn);
+template <int LPN, typename FT, int WORDS>
+const void *kernel_ptr(int nmodes) {
+    if (nmodes <= 3) return (const void *)k_mttkrp<LPN, FT, WORDS, 2>;
+    if (nmodes <= 5) return (const void *)k_mttkrp<LPN, FT, WORDS, 4>;
+    return (const void *)k_mttkrp<LPN, FT, WORDS, 7>;
+}
+
+template <typename FT, int WORDS>
+const void *pick_lpn(int lpn, int nmodes) {
+    switch (lpn) {
+        case 1: return kernel_ptr<1, FT, WORDS>(nmodes);
+        case 2: return kernel_ptr<2, FT, WORDS>(nmodes);
+        case 4: return kernel_ptr<4, FT, WORDS>(nmodes);
+        case 8: return kernel_ptr<8, FT, WORDS>(nmodes);
+        case 16: return kernel_ptr<16, FT, WORDS>(nmodes);
+        default: return kernel_ptr<32, FT, WORDS>(nmodes);
+    }
+}
+
+const void *pick_kernel(int lpn, int fdt, int words, int nmodes) {
+    if (fdt == ALTO_BF16)
+        return words == 2 ? pick_lpn<uint16_t, 2>(lpn, nmodes) : pick_lpn<uint16_t, 1>(lpn, nmodes);
+    return words == 2 ? pick_lpn<float, 2>(lpn, nmodes) : pick_lpn<float, 1>(lpn, nmodes);
 }
 
 struct DevProps {
@@ -321,10 +485,38 @@ alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt)
     int s2 = 1;
     while (s2 * 2 <= slots) s2 *= 2;
     p.table_slots = std::max(64, s2);
-    p.tile_nnz = 4 * p.table_slots;
-    p.accumulate = ALTO_ACC_F64;
+    // long tiles amortize the table flush; keep enough tiles to fill the GPU
+    uint64_t tile = 512;
+    while (tile < 16384 && tile * 8192 < h->info.nnz) tile *= 2;
+    p.tile_nnz = (int)tile;
+    p.accumulate = ALTO_ACC_F32;
     (void)fdt;
     return p;
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::array<int, 6>, alto_mttkrp_plan> g_tune_cache;
+
+std::array<int, 6> tune_key(const alto_tensor *h, int mode, int rank, int fdt) {
+    const double reuse = (double)h->info.nnz / (double)h->info.dims[mode];
+    const int lr = reuse > 0 ? (int)std::floor(std::log2(reuse)) : -64;
+    const int ln = h->info.nnz > 0 ? (int)std::floor(std::log2((double)h->info.nnz)) : -1;
+    return {h->info.nmodes, rank, h->info.index_words, fdt, lr, ln};
+}
+
+void record_tuned(alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan &p) {
+    h->tuned[mode][fdt][rank / 4] = p;
+    h->has_tuned[mode][fdt][rank / 4] = true;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[tune_key(h, mode, rank, fdt)] = p;
+}
+
+bool cached_tuned(const alto_tensor *h, int mode, int rank, int fdt, alto_mttkrp_plan *p) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(h, mode, rank, fdt));
+    if (it == g_tune_cache.end()) return false;
+    *p = it->second;
+    return true;
 }
 
 alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan *in,
@@ -332,6 +524,7 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
     alto_mttkrp_plan p = default_plan(h, mode, rank, fdt);
     const int ri = rank / 4;
     if (ri >= 0 && ri <= 32 && h->has_tuned[mode][fdt][ri]) p = h->tuned[mode][fdt][ri];
+    else if (ri >= 0 && ri <= 32) cached_tuned(h, mode, rank, fdt, &p);
     if (in) {
         if (in->conflict) p.conflict = in->conflict;
         if (in->tile_nnz) p.tile_nnz = in->tile_nnz;
@@ -339,7 +532,7 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
         if (in->table_slots) p.table_slots = in->table_slots;
         if (in->accumulate) p.accumulate = in->accumulate;
     }
-    if (p.accumulate != ALTO_ACC_F64 && p.accumulate != ALTO_ACC_F32) return fail(ALTO_ERR_ARG, "bad accumulate mode");
+    if (p.accumulate < ALTO_ACC_F64 || p.accumulate > ALTO_ACC_XCD_F64) return fail(ALTO_ERR_ARG, "bad accumulate mode");
     if (p.conflict != ALTO_CR_TILE && p.conflict != ALTO_CR_RUN) return fail(ALTO_ERR_ARG, "bad conflict mode");
     if (p.block_threads != 256) return fail(ALTO_ERR_ARG, "block_threads must be 256");
     if (p.tile_nnz < 1) return fail(ALTO_ERR_ARG, "tile_nnz must be positive");
@@ -384,8 +577,8 @@ alto_status ensure_ws(void **p, size_t *have, size_t need) {
     return ALTO_OK;
 }
 
-void fill_args(const alto_tensor *h, int mode, int rank, const void *const *factors, const alto_mttkrp_plan &p,
-               float *out32, double *out64, MttkrpArgs *a) {
+void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
+               const alto_mttkrp_plan &p, float *out32, double *out64, MttkrpArgs *a) {
     memset(a, 0, sizeof(*a));
     a->lp = h->lp;
     int k = 0;
@@ -395,6 +588,16 @@ void fill_args(const alto_tensor *h, int mode, int rank, const void *const *fact
             a->fac_other[k++] = factors[m];
         }
     a->dim_out = (uint32_t)h->info.dims[mode];
+    // 32-bit buffer offsets reach every factor row when each factor is below 2 GiB
+    const int fbytes = fdt == ALTO_BF16 ? 2 : 4;
+    a->buf32 = 1;
+    k = 0;
+    for (int m = 0; m < h->info.nmodes; m++) {
+        if (m == mode) continue;
+        const uint64_t bytes = h->info.dims[m] * (uint64_t)rank * fbytes;
+        if (bytes >= (uint64_t(1) << 31)) a->buf32 = 0;
+        a->fac_bytes[k++] = (uint32_t)(bytes < (uint64_t(1) << 31) ? bytes : 0);
+    }
     a->keys = h->keys;
     a->vals = h->vals;
     a->out32 = out32;
@@ -409,7 +612,9 @@ void fill_args(const alto_tensor *h, int mode, int rank, const void *const *fact
     a->rank = rank;
     a->nmodes = h->info.nmodes;
     a->tile_merge = p.conflict == ALTO_CR_TILE ? 1 : 0;
-    a->use64 = p.accumulate == ALTO_ACC_F64 ? 1 : 0;
+    a->use64 = (p.accumulate == ALTO_ACC_F64 || p.accumulate == ALTO_ACC_XCD_F64) ? 1 : 0;
+    a->copies = (p.accumulate == ALTO_ACC_XCD_F32 || p.accumulate == ALTO_ACC_XCD_F64) ? kXcdCopies : 1;
+    a->copy_stride = h->info.dims[mode] * (uint64_t)rank;
     int l2 = 0;
     while ((1 << l2) < p.table_slots) l2++;
     a->slots_log2 = l2;
@@ -418,7 +623,7 @@ void fill_args(const alto_tensor *h, int mode, int rank, const void *const *fact
 
 size_t lds_bytes(const MttkrpArgs &a, int threads) {
     const size_t S = a.tile_merge ? ((size_t)1 << a.slots_log2) : 0;
-    return (S + S * a.rank) * 4 + (size_t)threads * a.rec * 4;
+    return (2 * S + S * a.rank) * 4 + (size_t)threads * a.rec * 4;
 }
 
 // ---- optional per-launch timing with HIP events
@@ -476,7 +681,7 @@ void timing_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
 
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s) {
     const int lpn = lpn_for(a.rank);
-    const void *kern = pick_kernel(lpn, fdt, h->info.index_words);
+    const void *kern = pick_kernel(lpn, fdt, h->info.index_words, a.nmodes);
     const size_t lds = lds_bytes(a, threads);
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) {
@@ -505,24 +710,36 @@ alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, in
 alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
                        const alto_mttkrp_plan &p, hipStream_t s) {
     const uint64_t nout = h->info.dims[mode] * (uint64_t)rank;
+    const bool f64 = p.accumulate == ALTO_ACC_F64 || p.accumulate == ALTO_ACC_XCD_F64;
+    const int copies = (p.accumulate == ALTO_ACC_XCD_F32 || p.accumulate == ALTO_ACC_XCD_F64) ? kXcdCopies : 1;
+    const bool direct = p.accumulate == ALTO_ACC_F32;  // atomics straight into `out`
+    const unsigned g = grid_for(nout * copies, 256, 16384);
     double *out64 = nullptr;
-    if (p.accumulate == ALTO_ACC_F64) {
-        alto_status st = ensure_ws(&h->ws_acc, &h->ws_acc_bytes, nout * 8);
+    float *acc32 = out;
+    if (!direct) {
+        alto_status st = ensure_ws(&h->ws_acc, &h->ws_acc_bytes, nout * copies * (f64 ? 8 : 4));
         if (st != ALTO_OK) return st;
-        out64 = (double *)h->ws_acc;
-        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(nout, 256, 16384)), dim3(256), 0, s, out64, nout, 0.0);
+        if (f64) {
+            out64 = (double *)h->ws_acc;
+            hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, s, out64, nout * copies, 0.0);
+        } else {
+            acc32 = (float *)h->ws_acc;
+            hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, s, acc32, nout * copies, 0.f);
+        }
     } else {
-        hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(nout, 256, 16384)), dim3(256), 0, s, out, nout, 0.f);
+        hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, s, out, nout, 0.f);
     }
     ALTO_HIP(hipGetLastError());
     if (h->info.nnz > 0) {
         MttkrpArgs a;
-        fill_args(h, mode, rank, factors, p, out, out64, &a);
+        fill_args(h, mode, rank, fdt, factors, p, acc32, out64, &a);
         alto_status st = launch_mttkrp(h, fdt, a, p.block_threads, s);
         if (st != ALTO_OK) return st;
     }
-    if (p.accumulate == ALTO_ACC_F64) {
-        hipLaunchKernelGGL(k_round_f64, dim3(grid_for(nout, 256, 16384)), dim3(256), 0, s, out64, out, nout);
+    if (!direct) {
+        const unsigned g1 = grid_for(nout, 256, 16384);
+        if (f64) hipLaunchKernelGGL(k_sum_copies<double>, dim3(g1), dim3(256), 0, s, out64, copies, nout, out);
+        else hipLaunchKernelGGL(k_sum_copies<float>, dim3(g1), dim3(256), 0, s, acc32, copies, nout, out);
         ALTO_HIP(hipGetLastError());
     }
     return ALTO_OK;

@@ -55,8 +55,8 @@ alto_status make_plan(int nmodes, const uint64_t *dims, alto_info_t *info, LineP
     in.nmodes = nmodes;
     int total = 0, maxb = 0;
     for (int n = 0; n < nmodes; n++) {
-        if (dims[n] == 0 || dims[n] >= (uint64_t(1) << 32))
-            return fail(ALTO_ERR_ARG, "dims[" + std::to_string(n) + "] must be in 1..2^32-1");
+        if (dims[n] == 0 || dims[n] > (uint64_t(1) << 31))
+            return fail(ALTO_ERR_ARG, "dims[" + std::to_string(n) + "] must be in 1..2^31");
         in.dims[n] = dims[n];
         in.nbits[n] = ceil_log2(dims[n]);
         total += in.nbits[n];

@@ -107,3 +107,23 @@ def test_repeat_runs_agree():
     a = T.mttkrp(0, facs).cpu().numpy()
     b = T.mttkrp(0, facs).cpu().numpy()
     assert rel_fro(a.astype(np.float64), b.astype(np.float64)) <= 1e-6
+
+
+def test_autotune_records_a_plan_and_stays_exact():
+    X, T = built("c2s")
+    facs = factors_for(X, 16, seed=3)
+    refs = oracle_modes(X, facs)
+    gf = [torch.from_numpy(f).cuda() for f in facs]
+    for n in range(X.nmodes):
+        say(f"[mttkrp] autotune mode={n}")
+        out = torch.empty((X.dims[n], 16), device="cuda")
+        chosen = T.autotune(n, gf, out=out)
+        assert chosen == T.get_plan(n, 16)
+        assert rel_fro(out.cpu().numpy().astype(np.float64), refs[n]) <= TOL
+        got = T.mttkrp(n, gf).cpu().numpy().astype(np.float64)
+        assert rel_fro(got, refs[n]) <= TOL
+    # a second handle of the same class starts from the cached plan
+    coords, vals = upload(X)
+    T2 = alto.AltoTensor(X.dims, coords, vals)
+    assert T2.get_plan(2, 16) == T.get_plan(2, 16)
+    T2.free()
