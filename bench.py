@@ -92,6 +92,75 @@ def cpu_baseline(X, rank, budget_nnz):
     }
 
 
+COPY_BYTES = 1 << 30
+
+
+def traffic_driver(X, alto, torch, mfacs, outs, rank, fdt, plan):
+    """Counter-collection driver: one plain device copy of COPY_BYTES (the
+    calibration kernel), then two MTTKRP launches per mode with the plans the
+    bench uses.  Run under rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE)."""
+    T = alto.AltoTensor(X.dims, torch.from_numpy(X.coords).cuda(), torch.from_numpy(
+        X.vals.astype("float32")).cuda())
+    plans = [T.get_plan(n, rank, fdt) if plan is None else plan for n in range(X.nmodes)]
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    for n in range(X.nmodes):
+        for _ in range(2):
+            T.mttkrp(n, mfacs, out=outs[n], rank=rank, fdt=fdt, plan=plans[n])
+    torch.cuda.synchronize()
+    T.free()
+    log(f"[bench] traffic driver done; plans {plans}")
+
+
+def traffic_from(pmc_dirs, workload, nmodes):
+    """Turn two rocprofv3 --pmc runs of the driver (FETCH_SIZE, WRITE_SIZE;
+    KiB per dispatch) into HBM bytes per MTTKRP launch, each scaled by what the
+    same counter reads for the copy kernel of known size."""
+    import csv
+    import glob
+
+    per = {}
+    for d in pmc_dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows = list(csv.DictReader(open(f)))
+            for r in rows:
+                name, ctr, val = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+                per.setdefault(ctr, []).append((int(r.get("Dispatch_Id", 0) or 0), name, val))
+    out = {"copy_bytes": COPY_BYTES}
+    total = 0.0
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        recs = sorted(per.get(ctr, []))
+        mtt_recs = [(i, v) for i, n, v in recs if "k_mttkrp" in n][-2 * nmodes:]
+        if not mtt_recs:
+            raise SystemExit(f"no MTTKRP dispatches found for {ctr}")
+        first = mtt_recs[0][0]
+        # the calibration copy is the last copy dispatched before them
+        copy = [v for i, n, v in recs if "copyBuffer" in n and i < first]
+        mtt = [v for _, v in mtt_recs]
+        if not copy:
+            raise SystemExit(f"no copy dispatch found for {ctr}")
+        # the copy reads and writes COPY_BYTES: counter KiB per true byte
+        factor = copy[-1] * 1024.0 / COPY_BYTES
+        launches = [v * 1024.0 / factor for v in mtt]
+        out[ctr] = {"copy_kib": copy[-1], "factor": factor, "mttkrp_kib": mtt,
+                    "bytes_per_launch": sum(launches) / len(launches)}
+        total += out[ctr]["bytes_per_launch"]
+    out["bytes_per_launch"] = round(total)
+    out["kernel_sha"] = kernel_hash()
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            allrec = json.load(fh)
+    except (OSError, ValueError):
+        allrec = {}
+    allrec[workload] = out
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(allrec, fh, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,7 +172,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default=None, help="JSON MTTKRP plan override")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--traffic-driver", action="store_true", help="counter-collection driver (see traffic_driver)")
+    ap.add_argument("--traffic-from", nargs="+", default=None, help="rocprofv3 --pmc output dirs to summarize")
     args = ap.parse_args()
+    if args.traffic_from:
+        from synth import CONFIGS
+
+        name = f"{args.config}" + (f"-nnz{args.nnz}" if args.nnz else "")
+        traffic_from(args.traffic_from, name, len(CONFIGS[args.config]["dims"]))
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -157,6 +234,9 @@ def main():
             p = T.autotune(n, mfacs, out=outs[n], rank=rank, fdt=fdt)
             log(f"[bench] autotuned mode {n}: {p}")
         T.free()
+    if args.traffic_driver:
+        traffic_driver(X, alto, torch, mfacs, outs, rank, fdt, plan)
+        return
     for i in range(args.warmup):
         step()
         log(f"[bench] warmup step {i} done")
