@@ -236,10 +236,85 @@ alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *con
                              void *stream);
 
 /*
+ * One CP-ALS sweep of each of `count` tensors at once: for every mode step n,
+ * the MTTKRPs of all tensors that have a mode n run in one persistent
+ * launch per kernel variant (as alto_mttkrp_batched), around each tensor's
+ * own FP64 R x R solve and normalisation.  Per item as cpd_als_sweep_ex:
+ * hs[j], ranks[j], fdts[j], factors[j] (host array of device pointers),
+ * lambdas[j] (device [ranks[j]]).  Tensors may differ in order, dims and
+ * rank.  Results equal separate sweeps up to FP32 summation order.
+ */
+alto_status cpd_als_sweep_batched(int count, const alto_handle *hs /*host*/, const int *ranks /*host*/,
+                                  const int *fdts /*host*/, float *const *const *factors /*host[count]*/,
+                                  double *const *lambdas /*host[count] of device ptrs*/, void *stream);
+
+/*
  * Status flags of the last sweep on `stream` (host, synchronizes the stream):
  * bit n set when mode n used the pseudo-inverse fallback.
  */
 alto_status alto_sweep_flags(alto_handle h, void *stream, uint32_t *flags /*host*/);
+
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * Continuous-batching CP-ALS server (one per GPU; a native scheduler thread).
+ * Jobs are admitted while their estimated HBM footprint (ALTO tensor, build
+ * scratch, factors, BF16 shadows, sweep workspace) fits the free budget and
+ * an active slot is free; admitted tensors stay resident.  The scheduler
+ * runs rounds: one CP-ALS sweep of every active job with the MTTKRPs of all
+ * jobs batched (cpd_als_sweep_batched) on its compute stream, while newly
+ * admitted jobs are built on a second stream.  A job retires after `sweeps`
+ * sweeps; its factors (in place) and lambda_out then hold the result.
+ * Jobs whose footprint exceeds the whole budget are rejected
+ * (ALTO_ERR_BUDGET in their completion record).  All pointers in a job are
+ * device pointers owned by the caller and must stay valid until the job's
+ * completion record has been polled.
+ */
+typedef struct alto_server *alto_server_t;
+
+typedef struct {
+    int nmodes;
+    int rank;             /* multiple of 4, 4..64 */
+    int sweeps;           /* >= 1 */
+    int fdt;              /* alto_dtype of the MTTKRP factor reads */
+    uint64_t dims[ALTO_MAX_MODES];
+    uint64_t nnz;
+    const int64_t *coords[ALTO_MAX_MODES];  /* device [nnz] each */
+    const float *vals;                      /* device [nnz] */
+    float *factors[ALTO_MAX_MODES];         /* device dims[m] x rank, in/out */
+    double *lambda_out;                     /* device [rank] */
+    uint64_t user_tag;
+} alto_serve_job;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected, active, queued;
+    uint64_t bytes_in_use, bytes_peak;  /* admitted footprint (estimate) */
+    uint64_t sweeps_done, nnz_modes_done, rounds;
+} alto_serve_stats;
+
+typedef struct {
+    uint64_t user_tag;
+    int status;          /* ALTO_OK or the error of its build/sweep */
+    int sweeps;          /* sweeps completed */
+    double submit_s, admit_s, done_s;  /* seconds on the server's clock */
+    double sweep_ms_sum, sweep_ms_max; /* durations of the rounds it ran in */
+} alto_serve_done;
+
+/* budget_bytes: admitted-footprint cap; max_active: concurrent jobs. */
+alto_status alto_server_create(uint64_t budget_bytes, int max_active, alto_server_t *out /*host*/);
+/* Queue a job (copied; thread-safe).  Returns at once. */
+alto_status alto_server_submit(alto_server_t s, const alto_serve_job *job /*host*/);
+/* Move up to `max` completion records into out[]; *n receives the count. */
+alto_status alto_server_poll(alto_server_t s, alto_serve_done *out /*host*/, int max, int *n /*host*/);
+alto_status alto_server_stats(alto_server_t s, alto_serve_stats *out /*host*/);
+/* Block until every submitted job has completed or been rejected. */
+alto_status alto_server_drain(alto_server_t s);
+/* Per-sweep (job, round) latencies in ms, oldest first; *n = count copied. */
+alto_status alto_server_sweep_latencies(alto_server_t s, double *out /*host*/, uint64_t max, uint64_t *n);
+/* Stop the scheduler after draining and release everything. */
+alto_status alto_server_destroy(alto_server_t s);
+/* Estimated HBM footprint of a job (host, no GPU needed). */
+alto_status alto_serve_footprint(const alto_serve_job *job /*host*/, uint64_t *bytes /*host*/);
 
 /* ---------------------------------------------------------------- timing */
 

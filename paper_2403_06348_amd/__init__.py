@@ -269,3 +269,18 @@ def mttkrp_batched(items, stream=None):
     _check(_capi.lib().alto_mttkrp_batched(count, hs, modes, ranks, fdts, fptrs, outs, _stream(stream)),
            "alto_mttkrp_batched")
     return [it[3] for it in items]
+
+
+def sweep_batched(items, stream=None):
+    """items: list of (AltoTensor, factors (FP32 CUDA tensors), lam (FP64 CUDA
+    tensor), fdt).  One CP-ALS sweep of every tensor, MTTKRPs batched."""
+    count = len(items)
+    hs = (ctypes.c_void_p * count)(*[it[0].handle.value for it in items])
+    ranks = (ctypes.c_int * count)(*[int(it[1][0].shape[1]) for it in items])
+    fdts = (ctypes.c_int * count)(*[int(it[3]) if len(it) > 3 else F32 for it in items])
+    farrs = [(ctypes.c_void_p * it[0].nmodes)(*[f.data_ptr() for f in it[1]]) for it in items]
+    fptrs = (ctypes.c_void_p * count)(*[ctypes.cast(a, ctypes.c_void_p).value for a in farrs])
+    lams = (ctypes.c_void_p * count)(*[it[2].data_ptr() for it in items])
+    _check(_capi.lib().cpd_als_sweep_batched(count, hs, ranks, fdts, fptrs, lams, _stream(stream)),
+           "cpd_als_sweep_batched")
+    return [it[2] for it in items]

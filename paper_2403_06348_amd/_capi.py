@@ -97,18 +97,12 @@ class ServeJob(ctypes.Structure):
 
 
 class ServeStats(ctypes.Structure):
-    _fields_ = [
-        ("submitted", ctypes.c_uint64),
-        ("admitted", ctypes.c_uint64),
-        ("completed", ctypes.c_uint64),
-        ("rejected", ctypes.c_uint64),
-        ("active", ctypes.c_uint64),
-        ("queued", ctypes.c_uint64),
-        ("bytes_in_use", ctypes.c_uint64),
-        ("bytes_peak", ctypes.c_uint64),
-        ("sweeps_done", ctypes.c_uint64),
-        ("nnz_modes_done", ctypes.c_uint64),
-    ]
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "admitted", "completed", "rejected", "active", "queued", "bytes_in_use", "bytes_peak",
+        "sweeps_done", "nnz_modes_done", "rounds")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class ServeDone(ctypes.Structure):
@@ -122,6 +116,9 @@ class ServeDone(ctypes.Structure):
         ("sweep_ms_sum", ctypes.c_double),
         ("sweep_ms_max", ctypes.c_double),
     ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 P = ctypes.c_void_p
@@ -147,6 +144,15 @@ SIGNATURES = {
     "cpd_als_sweep": (I32, [P, I32, P, P, P]),
     "cpd_als_sweep_ex": (I32, [P, I32, I32, P, P, P]),
     "alto_sweep_flags": (I32, [P, P, ctypes.POINTER(ctypes.c_uint32)]),
+    "cpd_als_sweep_batched": (I32, [I32, P, P, P, P, P, P]),
+    "alto_server_create": (I32, [U64, I32, ctypes.POINTER(P)]),
+    "alto_server_submit": (I32, [P, ctypes.POINTER(ServeJob)]),
+    "alto_server_poll": (I32, [P, P, I32, ctypes.POINTER(I32)]),
+    "alto_server_stats": (I32, [P, ctypes.POINTER(ServeStats)]),
+    "alto_server_drain": (I32, [P]),
+    "alto_server_sweep_latencies": (I32, [P, P, U64, ctypes.POINTER(U64)]),
+    "alto_server_destroy": (I32, [P]),
+    "alto_serve_footprint": (I32, [ctypes.POINTER(ServeJob), ctypes.POINTER(U64)]),
     "alto_timing_enable": (I32, [I32]),
     "alto_timing_read": (I32, [ctypes.POINTER(U64), ctypes.POINTER(ctypes.c_double)]),
     "alto_release_cached_memory": (I32, []),

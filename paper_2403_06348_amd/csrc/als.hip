@@ -17,7 +17,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "alto_internal.h"
 #include "device_util.h"
@@ -343,14 +345,9 @@ unsigned partial_blocks(uint64_t I) {
 }
 
 }  // namespace
-}  // namespace alto
 
-using namespace alto;
-
-extern "C" {
-
-alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *const *factors, double *lambda,
-                             void *stream) {
+alto_status sweep_begin(alto_tensor *h, int rank, int fdt, float *const *factors, const double *lambda,
+                        hipStream_t s) {
     ALTO_CHECK_HANDLE(h);
     const int N = h->info.nmodes;
     const int R = rank;
@@ -361,7 +358,6 @@ alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *con
         if (!factors[m]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(m) + "] is NULL");
         if ((uintptr_t)factors[m] & 15) return fail(ALTO_ERR_ARG, "factors must be 16-byte aligned");
     }
-    hipStream_t s = (hipStream_t)stream;
     uint64_t maxI = 0;
     for (int m = 0; m < N; m++) maxI = h->info.dims[m] > maxI ? h->info.dims[m] : maxI;
     const size_t rr = (size_t)R * R;
@@ -380,11 +376,8 @@ alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *con
         }
     }
     double *grams = (double *)h->ws_sweep;
-    double *W = grams + N * rr;
-    double *partials = W + rr;
-    double *lam_ws = partials + (size_t)kPartials * rr;
+    double *partials = grams + N * rr + rr;
     const int ent = ent_for(R);
-
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, h->ws_flags, (uint64_t)1, 0u);
     for (int m = 0; m < N; m++) {
         const uint64_t I = h->info.dims[m];
@@ -396,23 +389,114 @@ alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *con
                                h->ws_bf16[m]);
     }
     ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+void sweep_factor_ptrs(const alto_tensor *h, int fdt, float *const *factors, const void **fptr) {
+    for (int m = 0; m < h->info.nmodes; m++)
+        fptr[m] = fdt == ALTO_BF16 ? (const void *)h->ws_bf16[m] : (const void *)factors[m];
+}
+
+alto_status sweep_pre(alto_tensor *h, int n, int rank, hipStream_t s) {
+    const size_t rr = (size_t)rank * rank;
+    double *grams = (double *)h->ws_sweep;
+    double *W = grams + h->info.nmodes * rr;
+    hipLaunchKernelGGL(k_als_prepare, dim3(1), dim3(kThreads), 3 * rr * 8, s, grams, h->info.nmodes, n, rank, W,
+                       h->ws_flags);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+alto_status sweep_post(alto_tensor *h, int n, int rank, int fdt, float *const *factors, double *lambda,
+                       hipStream_t s) {
+    const int R = rank;
+    const size_t rr = (size_t)R * R;
+    double *grams = (double *)h->ws_sweep;
+    double *W = grams + h->info.nmodes * rr;
+    double *partials = W + rr;
+    double *lam_ws = partials + (size_t)kPartials * rr;
+    const uint64_t I = h->info.dims[n];
+    const unsigned P = partial_blocks(I);
+    const int ent = ent_for(R);
+    ALTO_ENT_DISPATCH(ent, k_als_apply, dim3(P), dim3(kThreads), 0, s, h->ws_m, W, factors[n], I, R, partials);
+    hipLaunchKernelGGL(k_als_finalize, dim3(1), dim3(kThreads), 0, s, partials, (int)P, R, grams + n * rr, lam_ws,
+                       lambda);
+    hipLaunchKernelGGL(k_als_normalize, dim3(grid_for(I * R, 256, 16384)), dim3(256), 0, s, factors[n], I, R, lam_ws,
+                       fdt == ALTO_BF16 ? h->ws_bf16[n] : nullptr);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+}  // namespace alto
+
+using namespace alto;
+
+extern "C" {
+
+alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *const *factors, double *lambda,
+                             void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    alto_status st = sweep_begin(h, rank, fdt, factors, lambda, s);
+    if (st != ALTO_OK) return st;
     const void *fptr[ALTO_MAX_MODES];
-    for (int m = 0; m < N; m++) fptr[m] = fdt == ALTO_BF16 ? (const void *)h->ws_bf16[m] : (const void *)factors[m];
-    for (int n = 0; n < N; n++) {
-        const uint64_t I = h->info.dims[n];
-        hipLaunchKernelGGL(k_als_prepare, dim3(1), dim3(kThreads), 3 * rr * 8, s, grams, N, n, R, W, h->ws_flags);
+    sweep_factor_ptrs(h, fdt, factors, fptr);
+    for (int n = 0; n < h->info.nmodes; n++) {
+        st = sweep_pre(h, n, rank, s);
+        if (st != ALTO_OK) return st;
         alto_mttkrp_plan p;
-        st = resolve_plan(h, n, R, fdt, nullptr, &p);
+        st = resolve_plan(h, n, rank, fdt, nullptr, &p);
         if (st != ALTO_OK) return st;
-        st = run_mttkrp(h, n, R, fdt, fptr, h->ws_m, p, s);
+        st = run_mttkrp(h, n, rank, fdt, fptr, h->ws_m, p, s);
         if (st != ALTO_OK) return st;
-        const unsigned P = partial_blocks(I);
-        ALTO_ENT_DISPATCH(ent, k_als_apply, dim3(P), dim3(kThreads), 0, s, h->ws_m, W, factors[n], I, R, partials);
-        hipLaunchKernelGGL(k_als_finalize, dim3(1), dim3(kThreads), 0, s, partials, (int)P, R, grams + n * rr, lam_ws,
-                           n == N - 1 ? lambda : nullptr);
-        hipLaunchKernelGGL(k_als_normalize, dim3(grid_for(I * R, 256, 16384)), dim3(256), 0, s, factors[n], I, R,
-                           lam_ws, fdt == ALTO_BF16 ? h->ws_bf16[n] : nullptr);
-        ALTO_HIP(hipGetLastError());
+        st = sweep_post(h, n, rank, fdt, factors, n == h->info.nmodes - 1 ? lambda : nullptr, s);
+        if (st != ALTO_OK) return st;
+    }
+    return ALTO_OK;
+}
+
+alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *ranks, const int *fdts,
+                                  float *const *const *factors, double *const *lambdas, void *stream) {
+    if (count < 0) return fail(ALTO_ERR_ARG, "count < 0");
+    if (count == 0) return ALTO_OK;
+    if (!hs || !ranks || !fdts || !factors || !lambdas) return fail(ALTO_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int maxN = 0;
+    for (int j = 0; j < count; j++) {
+        if (!factors[j]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(j) + "] is NULL");
+        alto_status st = sweep_begin(hs[j], ranks[j], fdts[j], factors[j], lambdas[j], s);
+        if (st != ALTO_OK) return fail(st, "item " + std::to_string(j) + ": " + alto_last_error());
+        maxN = std::max(maxN, hs[j]->info.nmodes);
+    }
+    std::vector<const void *> fptr((size_t)count * ALTO_MAX_MODES);
+    for (int j = 0; j < count; j++) sweep_factor_ptrs(hs[j], fdts[j], factors[j], &fptr[(size_t)j * ALTO_MAX_MODES]);
+    std::vector<alto_handle> bh;
+    std::vector<int> bm, br, bf;
+    std::vector<const void *const *> bfac;
+    std::vector<float *> bout;
+    for (int n = 0; n < maxN; n++) {
+        bh.clear(); bm.clear(); br.clear(); bf.clear(); bfac.clear(); bout.clear();
+        for (int j = 0; j < count; j++) {
+            if (n >= hs[j]->info.nmodes) continue;
+            alto_status st = sweep_pre(hs[j], n, ranks[j], s);
+            if (st != ALTO_OK) return st;
+            bh.push_back(hs[j]);
+            bm.push_back(n);
+            br.push_back(ranks[j]);
+            bf.push_back(fdts[j]);
+            bfac.push_back(&fptr[(size_t)j * ALTO_MAX_MODES]);
+            bout.push_back(hs[j]->ws_m);
+        }
+        // the MTTKRPs of mode n of every job in one persistent launch per
+        // kernel variant
+        alto_status st = batched_run((int)bh.size(), bh.data(), bm.data(), br.data(), bf.data(), bfac.data(),
+                                     bout.data(), s);
+        if (st != ALTO_OK) return st;
+        for (int j = 0; j < count; j++) {
+            if (n >= hs[j]->info.nmodes) continue;
+            st = sweep_post(hs[j], n, ranks[j], fdts[j], factors[j],
+                            n == hs[j]->info.nmodes - 1 ? lambdas[j] : nullptr, s);
+            if (st != ALTO_OK) return st;
+        }
     }
     return ALTO_OK;
 }

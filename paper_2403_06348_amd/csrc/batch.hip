@@ -13,6 +13,171 @@
 #include "memory.h"
 #include "mttkrp.h"
 
+namespace alto {
+namespace {
+
+// Per-stream device staging of job descriptors: calls on one stream reuse
+// its buffer in stream order; calls on different streams never share one.
+struct Staging {
+    void *dev = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_stage_mu;
+std::map<std::pair<int, hipStream_t>, Staging> g_stage;
+
+// Tuned (tile, table rows) per kernel-variant group and total-size class.
+std::mutex g_btune_mu;
+std::map<std::array<int, 6>, std::pair<int, int>> g_btune;
+
+struct Group {
+    int lpn, fdt, words, maxo;
+    std::vector<int> items;
+};
+
+int maxo_of(int nmodes) { return nmodes <= 3 ? 2 : (nmodes <= 5 ? 4 : 7); }
+
+alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes, const int *ranks,
+                         const void *const *const *factors, float *const *outs, int tile, int slots_factor,
+                         hipStream_t s, int dev) {
+    const int nj = (int)g.items.size();
+    std::vector<MttkrpArgs> jobs(nj);
+    std::vector<uint64_t> prefix(nj + 1, 0), oprefix(nj + 1, 0);
+    size_t lds = 0;
+    for (int k = 0; k < nj; k++) {
+        const int j = g.items[k];
+        alto_tensor *h = hs[j];
+        alto_mttkrp_plan p = default_plan(h, modes[j], ranks[j], g.fdt);
+        p.conflict = ALTO_CR_TILE;
+        p.accumulate = ALTO_ACC_F32;
+        p.tile_nnz = tile;
+        p.table_slots = std::max(16, p.table_slots * slots_factor / 2);
+        fill_args(h, modes[j], ranks[j], g.fdt, factors[j], p, outs[j], nullptr, &jobs[k]);
+        jobs[k].xcd_map = 0;
+        const uint64_t tiles = h->info.nnz == 0 ? 0 : jobs[k].ntiles;
+        prefix[k + 1] = prefix[k] + tiles;
+        oprefix[k + 1] = oprefix[k] + h->info.dims[modes[j]] * (uint64_t)ranks[j];
+        lds = std::max(lds, lds_bytes(jobs[k], 256));
+    }
+    const size_t jb = sizeof(MttkrpArgs) * nj, pb = 8 * (nj + 1);
+    const size_t need = jb + 2 * pb;
+    Staging *st;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        st = &g_stage[{dev, s}];
+    }
+    if (st->bytes < need) {
+        if (st->dev) {
+            ALTO_HIP(hipStreamSynchronize(s));
+            dev_free(st->dev);
+            st->dev = nullptr;
+            st->bytes = 0;
+        }
+        if (dev_alloc(&st->dev, need) != hipSuccess) return fail(ALTO_ERR_OOM, "batch staging allocation failed");
+        st->bytes = need;
+    }
+    std::vector<char> host(need);
+    memcpy(host.data(), jobs.data(), jb);
+    memcpy(host.data() + jb, prefix.data(), pb);
+    memcpy(host.data() + jb + pb, oprefix.data(), pb);
+    ALTO_HIP(hipMemcpyAsync(st->dev, host.data(), need, hipMemcpyHostToDevice, s));
+    const MttkrpArgs *djobs = (const MttkrpArgs *)st->dev;
+    const uint64_t *dprefix = (const uint64_t *)((char *)st->dev + jb);
+    const uint64_t *doprefix = (const uint64_t *)((char *)st->dev + jb + pb);
+    {
+        void *args[] = {(void *)&djobs, (void *)&doprefix, (void *)&nj};
+        const unsigned g0 = grid_for(oprefix[nj], 256, 8192);
+        ALTO_HIP(hipLaunchKernel(zero_outputs_kernel(), dim3(g0), dim3(256), args, 0, s));
+    }
+    if (prefix[nj] == 0) return ALTO_OK;
+    const void *kern = pick_kernel(g.lpn, g.fdt, g.words, jobs[0].nmodes, true);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        occ = 1;
+    }
+    uint64_t grid = (uint64_t)device_cus(dev) * occ;
+    int xcd_map = 1;
+    if (grid >= prefix[nj]) {
+        grid = prefix[nj];
+        xcd_map = 0;
+    } else {
+        grid = grid / 8 * 8;
+    }
+    void *args[] = {(void *)&djobs, (void *)&dprefix, (void *)&nj, (void *)&xcd_map};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = timing_begin(s, &e0, &e1);
+    ALTO_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(256), args, lds, s));
+    if (timed) timing_end(s, e0, e1);
+    return ALTO_OK;
+}
+
+}  // namespace
+
+alto_status batched_run(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
+                        const void *const *const *factors, float *const *outs, hipStream_t s) {
+    int dev = 0;
+    ALTO_HIP(hipGetDevice(&dev));
+    std::map<std::array<int, 4>, Group> groups;
+    for (int j = 0; j < count; j++) {
+        const std::array<int, 4> key = {lpn_for(ranks[j]), fdts[j], hs[j]->info.index_words,
+                                        maxo_of(hs[j]->info.nmodes)};
+        Group &g = groups[key];
+        g.lpn = key[0];
+        g.fdt = key[1];
+        g.words = key[2];
+        g.maxo = key[3];
+        g.items.push_back(j);
+    }
+    for (auto &kv : groups) {
+        const Group &g = kv.second;
+        uint64_t nnz = 0;
+        for (int j : g.items) nnz += hs[j]->info.nnz;
+        const int ln = nnz > 0 ? (int)std::floor(std::log2((double)nnz)) : -1;
+        const std::array<int, 6> tkey = {g.lpn, g.fdt, g.words, g.maxo, ln, (int)std::min<size_t>(g.items.size(), 64)};
+        std::pair<int, int> tuned = {0, 0};
+        {
+            std::lock_guard<std::mutex> lk(g_btune_mu);
+            auto it = g_btune.find(tkey);
+            if (it != g_btune.end()) tuned = it->second;
+        }
+        if (tuned.first == 0) {
+            // first sight of this group class: time a few (tile, table) plans
+            hipEvent_t e0, e1;
+            ALTO_HIP(hipEventCreate(&e0));
+            ALTO_HIP(hipEventCreate(&e1));
+            float best = 1e30f;
+            std::pair<int, int> bestp = {4096, 2};
+            for (int tile : {1024, 4096, 16384}) {
+                for (int f : {2, 4}) {
+                    alto_status st = launch_group(g, hs, modes, ranks, factors, outs, tile, f, s, dev);
+                    if (st != ALTO_OK) return st;
+                    ALTO_HIP(hipEventRecord(e0, s));
+                    st = launch_group(g, hs, modes, ranks, factors, outs, tile, f, s, dev);
+                    if (st != ALTO_OK) return st;
+                    ALTO_HIP(hipEventRecord(e1, s));
+                    ALTO_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    ALTO_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) {
+                        best = ms;
+                        bestp = {tile, f};
+                    }
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            tuned = bestp;
+            std::lock_guard<std::mutex> lk(g_btune_mu);
+            g_btune[tkey] = tuned;
+        }
+        alto_status st = launch_group(g, hs, modes, ranks, factors, outs, tuned.first, tuned.second, s, dev);
+        if (st != ALTO_OK) return st;
+    }
+    return ALTO_OK;
+}
+
+}  // namespace alto
+
 using namespace alto;
 
 extern "C" {
@@ -82,7 +247,15 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
 
 alto_status alto_mttkrp_batched(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
                                 const void *const *const *factors, float *const *outs, void *stream) {
-    return fail(ALTO_ERR_ARG, "batched MTTKRP not available yet");
+    if (count < 0) return fail(ALTO_ERR_ARG, "count < 0");
+    if (count == 0) return ALTO_OK;
+    if (!hs || !modes || !ranks || !fdts || !factors || !outs) return fail(ALTO_ERR_ARG, "NULL argument");
+    for (int j = 0; j < count; j++) {
+        if (!factors[j]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(j) + "] is NULL");
+        alto_status st = check_mttkrp_args(hs[j], modes[j], ranks[j], fdts[j], factors[j], outs[j]);
+        if (st != ALTO_OK) return fail(st, "item " + std::to_string(j) + ": " + alto_last_error());
+    }
+    return batched_run(count, hs, modes, ranks, fdts, factors, outs, (hipStream_t)stream);
 }
 
 }  // extern "C"

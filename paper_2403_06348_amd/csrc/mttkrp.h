@@ -51,6 +51,20 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
 size_t lds_bytes(const MttkrpArgs &a, int threads);
 int lpn_for(int rank);
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s);
+const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch);
+const void *zero_outputs_kernel();
+int device_cus(int dev);
+
+// batched MTTKRP (batch.hip), arguments already validated
+alto_status batched_run(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
+                        const void *const *const *factors, float *const *outs, hipStream_t s);
+
+// CP-ALS sweep phases (als.hip)
+alto_status sweep_begin(alto_tensor *h, int rank, int fdt, float *const *factors, const double *lambda, hipStream_t s);
+void sweep_factor_ptrs(const alto_tensor *h, int fdt, float *const *factors, const void **fptr);
+alto_status sweep_pre(alto_tensor *h, int n, int rank, hipStream_t s);
+alto_status sweep_post(alto_tensor *h, int n, int rank, int fdt, float *const *factors, double *lambda,
+                       hipStream_t s);
 bool timing_begin(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1);
 void timing_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 

@@ -168,10 +168,10 @@ __device__ inline uint32_t rec_coord(const uint4 &h, const uint4 &h2, int k) {
 
 // Kernel variants: MAXO = most other modes handled with fully unrolled
 // gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
+// Tiles [t0, t1) of one tensor's line, processed by one workgroup.  The LDS
+// table is initialized here and fully flushed by the last tile.
 template <int LPN, typename FT, int WORDS, int MAXO>
-__global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
-    extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ uint32_t nkeep;
+__device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep, uint64_t t0, uint64_t t1) {
     // nonzeros gathered together per group
     constexpr int SB = MAXO == 2 ? (LPN < 4 ? LPN : 4) : (LPN < 2 ? LPN : 2);
     const int S = a.tile_merge ? (1 << a.slots_log2) : 0;
@@ -197,14 +197,6 @@ __global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
         for (int i = tid; i < S * a.rank; i += blockDim.x) tval[i] = 0.f;
         __syncthreads();
     }
-
-    // Each workgroup owns one contiguous stretch of tiles (a line segment
-    // in the paper's sense); the stretches of the workgroups that share an
-    // XCD are neighbours on the line, so they share factor rows in its L2.
-    const uint32_t G = gridDim.x;
-    const uint32_t rr = a.xcd_map ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
-    const uint64_t t0 = (a.ntiles * rr) / G;
-    const uint64_t t1 = (a.ntiles * (rr + 1)) / G;
 
     for (uint64_t t = t0; t < t1; t++) {
         const uint64_t ts = t * a.tq + (t * a.tr) / a.ntiles;
@@ -413,6 +405,66 @@ __global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
     }
 }
 
+// Balanced stretch [g0, g1) of `total` tiles for this workgroup.  The
+// stretches of the workgroups that share an XCD (block id mod 8) are
+// neighbours on the line, so the factor rows they touch share its L2.
+__device__ inline void stretch_of(uint64_t total, int xcd_map, uint64_t *g0, uint64_t *g1) {
+    const uint32_t G = gridDim.x;
+    const uint32_t rr = xcd_map ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+    *g0 = (total * rr) / G;
+    *g1 = (total * (rr + 1)) / G;
+}
+
+// Kernel variants: MAXO = most other modes handled with fully unrolled
+// gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
+template <int LPN, typename FT, int WORDS, int MAXO>
+__global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ uint32_t nkeep;
+    uint64_t t0, t1;
+    stretch_of(a.ntiles, a.xcd_map, &t0, &t1);
+    mttkrp_stretch<LPN, FT, WORDS, MAXO>(a, smem, nkeep, t0, t1);
+}
+
+// Many tensors in one persistent launch: the tiles of all jobs form one
+// list (prefix[j] = first tile of job j); each workgroup drains a balanced
+// stretch of it, crossing job boundaries.
+template <int LPN, typename FT, int WORDS, int MAXO>
+__global__ __launch_bounds__(256) void k_mttkrp_batch(const MttkrpArgs *__restrict__ jobs,
+                                                      const uint64_t *__restrict__ prefix, int njobs, int xcd_map) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ uint32_t nkeep;
+    uint64_t g0, g1;
+    stretch_of(prefix[njobs], xcd_map, &g0, &g1);
+    // first job whose tiles reach past g0
+    int lo = 0, hi = njobs;
+    while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (prefix[mid + 1] <= g0) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int j = lo; j < njobs && prefix[j] < g1; j++) {
+        const uint64_t a0 = prefix[j], a1 = prefix[j + 1];
+        const uint64_t t0 = (g0 > a0 ? g0 : a0) - a0, t1 = (g1 < a1 ? g1 : a1) - a0;
+        if (t0 < t1) {
+            mttkrp_stretch<LPN, FT, WORDS, MAXO>(jobs[j], smem, nkeep, t0, t1);
+            __syncthreads();
+        }
+    }
+}
+
+// Zero every job's output (grid-stride over the concatenated outputs).
+__global__ void k_zero_outputs(const MttkrpArgs *__restrict__ jobs, const uint64_t *__restrict__ out_prefix,
+                               int njobs) {
+    const uint64_t total = out_prefix[njobs];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    int j = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        while (out_prefix[j + 1] <= i) j++;
+        jobs[j].out32[i - out_prefix[j]] = 0.f;
+    }
+}
+
 // out = FP32 rounding of the FP64 sum over `copies` partial outputs.
 template <typename T>
 __global__ void k_sum_copies(const T *__restrict__ in, int copies, uint64_t n, float *__restrict__ out) {
@@ -425,33 +477,48 @@ __global__ void k_sum_copies(const T *__restrict__ in, int copies, uint64_t n, f
 }
 
 template <int LPN, typename FT, int WORDS>
-const void *kernel_ptr(int nmodes) {
-    if (nmodes <= 3) return (const void *)k_mttkrp<LPN, FT, WORDS, 2>;
-    if (nmodes <= 5) return (const void *)k_mttkrp<LPN, FT, WORDS, 4>;
-    return (const void *)k_mttkrp<LPN, FT, WORDS, 7>;
+const void *kernel_ptr(int nmodes, bool batch) {
+    if (nmodes <= 3)
+        return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 2> : (const void *)k_mttkrp<LPN, FT, WORDS, 2>;
+    if (nmodes <= 5)
+        return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 4> : (const void *)k_mttkrp<LPN, FT, WORDS, 4>;
+    return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 7> : (const void *)k_mttkrp<LPN, FT, WORDS, 7>;
 }
 
 template <typename FT, int WORDS>
-const void *pick_lpn(int lpn, int nmodes) {
+const void *pick_lpn(int lpn, int nmodes, bool batch) {
     switch (lpn) {
-        case 1: return kernel_ptr<1, FT, WORDS>(nmodes);
-        case 2: return kernel_ptr<2, FT, WORDS>(nmodes);
-        case 4: return kernel_ptr<4, FT, WORDS>(nmodes);
-        case 8: return kernel_ptr<8, FT, WORDS>(nmodes);
-        case 16: return kernel_ptr<16, FT, WORDS>(nmodes);
-        default: return kernel_ptr<32, FT, WORDS>(nmodes);
+        case 1: return kernel_ptr<1, FT, WORDS>(nmodes, batch);
+        case 2: return kernel_ptr<2, FT, WORDS>(nmodes, batch);
+        case 4: return kernel_ptr<4, FT, WORDS>(nmodes, batch);
+        case 8: return kernel_ptr<8, FT, WORDS>(nmodes, batch);
+        case 16: return kernel_ptr<16, FT, WORDS>(nmodes, batch);
+        default: return kernel_ptr<32, FT, WORDS>(nmodes, batch);
     }
 }
 
-const void *pick_kernel(int lpn, int fdt, int words, int nmodes) {
+}  // namespace
+
+const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch) {
     if (fdt == ALTO_BF16)
-        return words == 2 ? pick_lpn<uint16_t, 2>(lpn, nmodes) : pick_lpn<uint16_t, 1>(lpn, nmodes);
-    return words == 2 ? pick_lpn<float, 2>(lpn, nmodes) : pick_lpn<float, 1>(lpn, nmodes);
+        return words == 2 ? pick_lpn<uint16_t, 2>(lpn, nmodes, batch) : pick_lpn<uint16_t, 1>(lpn, nmodes, batch);
+    return words == 2 ? pick_lpn<float, 2>(lpn, nmodes, batch) : pick_lpn<float, 1>(lpn, nmodes, batch);
 }
+
+const void *zero_outputs_kernel() { return (const void *)k_zero_outputs; }
+
+namespace {
 
 struct DevProps {
     int cus = 0;
 };
+
+DevProps &props(int dev);
+}  // namespace
+
+int device_cus(int dev) { return props(dev).cus; }
+
+namespace {
 
 DevProps &props(int dev) {
     static DevProps p[64];
@@ -681,7 +748,7 @@ void timing_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
 
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s) {
     const int lpn = lpn_for(a.rank);
-    const void *kern = pick_kernel(lpn, fdt, h->info.index_words, a.nmodes);
+    const void *kern = pick_kernel(lpn, fdt, h->info.index_words, a.nmodes, false);
     const size_t lds = lds_bytes(a, threads);
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) {

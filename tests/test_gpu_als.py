@@ -113,3 +113,54 @@ def test_sweep_pseudoinverse_fallback():
     assert not ok
     assert rel_fro(got0, ref0) <= 1e-4
     T.free()
+
+
+def test_sweep_graph_capture_replays_match_eager():
+    """The whole sweep captured in one HIP graph; every replay is checked
+    against an eager sweep from the same factors, with eager work and
+    synchronizations between the replays."""
+    X = case("c2s")
+    coords, vals = upload(X)
+    T = alto.AltoTensor(X.dims, coords, vals)
+    facs = factors_for(X, 16, seed=8)
+    gf = [torch.from_numpy(f.copy()).cuda() for f in facs]
+    lam = torch.empty(16, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        T.sweep([g.clone() for g in gf], lam=lam)  # allocates the workspace
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    start = [g.clone() for g in gf]
+    say("[als] capture sweep")
+    with torch.cuda.graph(graph, stream=side):
+        T.sweep(gf, lam=lam)
+    torch.cuda.synchronize()
+    for g, s0 in zip(gf, start):
+        g.copy_(s0)
+    eager = [g.clone() for g in start]
+    eager_lam = torch.empty_like(lam)
+    for rep in range(3):
+        before = [g.cpu().numpy().astype(np.float64) for g in gf]
+        graph.replay()
+        torch.cuda.synchronize()
+        T.sweep(eager, lam=eager_lam)  # eager sweep from the same state
+        torch.cuda.synchronize()
+        after = [g.cpu().numpy().astype(np.float64) for g in gf]
+        for n in range(X.nmodes):
+            # V of mode n from the factors both runs held at that point
+            cur = [after[m] if m < n else before[m] for m in range(X.nmodes)]
+            V = np.ones((16, 16))
+            for m in range(X.nmodes):
+                if m != n:
+                    V *= cur[m].T @ cur[m]
+            # both runs are within the MTTKRP gate (1e-5) of the exact
+            # update, amplified by cond(V); they differ only in FP32
+            # summation order
+            tol = max(1e-5, 2e-5 * np.linalg.cond(V))
+            e = rel_fro(after[n], eager[n].cpu().numpy().astype(np.float64))
+            say(f"    replay {rep} mode {n}: rel diff {e:.2e} (tol {tol:.1e})")
+            assert e <= tol
+        assert rel_fro(lam.cpu().numpy(), eager_lam.cpu().numpy()) <= tol
+        for g, ge in zip(gf, eager):  # continue both from the same state
+            ge.copy_(g)
+    T.free()

@@ -1,0 +1,102 @@
+"""Batched MTTKRP (many tensors of uneven nnz in one persistent launch per
+kernel variant) must give each tensor's oracle result, as alone."""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_cases import rel_fro, say, vals32
+from synth import make_factors, zipf_tensor
+
+pytestmark = pytest.mark.gpu
+
+alto = pytest.importorskip("paper_2403_06348_amd")
+torch = pytest.importorskip("torch")
+
+
+def job_specs():
+    # (dims, nnz, exponents, rank, seed): 3-5 modes, 1e3..2e5 nonzeros,
+    # one 100-bit index, one empty tensor
+    return [
+        ((3000, 2000, 500), 20_000, (1.2, 1.2, 1.2), 16, 31),
+        ((100_000, 70_000, 1_000), 150_000, (1.2, 1.2, 1.2), 16, 32),
+        ((5000, 300, 20, 4000), 60_000, (1.2, None, None, 1.2), 8, 33),
+        ((2**20, 2**20, 2**20, 2**20, 2**20), 40_000, (1.2,) * 5, 32, 34),
+        ((1000, 1000, 1000), 3_000, (None, None, None), 16, 35),
+        ((9_000, 8_000, 7_000, 6_000), 90_000, (1.2,) * 4, 32, 36),
+        ((500, 400, 300), 0, (1.2, 1.2, 1.2), 16, 37),
+    ]
+
+
+def test_batched_matches_oracle_and_alone():
+    torch.cuda.synchronize()
+    jobs = []
+    for dims, nnz, ex, R, seed in job_specs():
+        X = zipf_tensor(dims, nnz, ex, seed=seed)
+        T = alto.AltoTensor(X.dims, torch.from_numpy(X.coords).cuda(), torch.from_numpy(vals32(X)).cuda())
+        facs = make_factors(X.dims, R, seed=seed)
+        jobs.append((X, T, facs, [torch.from_numpy(f).cuda() for f in facs], R))
+    for rep in range(2):  # the first call tunes the group plans, the second reuses them
+        items = []
+        for k, (X, T, facs, gf, R) in enumerate(jobs):
+            mode = k % X.nmodes
+            out = torch.full((X.dims[mode], R), 7.0, device="cuda")
+            items.append((T, mode, gf, out, alto.F32))
+        say(f"[batched] call {rep} with {len(items)} items")
+        alto.mttkrp_batched(items)
+        torch.cuda.synchronize()
+        for k, ((X, T, facs, gf, R), it) in enumerate(zip(jobs, items)):
+            mode = it[1]
+            got = it[3].cpu().numpy().astype(np.float64)
+            ref = oracle.mttkrp(X.dims, X.coords, vals32(X).astype(np.float64),
+                                [f.astype(np.float64) for f in facs], mode)
+            if X.nnz == 0:
+                assert not got.any()
+                continue
+            e = rel_fro(got, ref)
+            alone = T.mttkrp(mode, gf).cpu().numpy().astype(np.float64)
+            say(f"    item {k}: nnz={X.nnz} N={X.nmodes} R={R} mode={mode} err {e:.2e}")
+            assert e <= 1e-5
+            assert rel_fro(got, alone) <= 2e-6
+    for X, T, *_ in jobs:
+        T.free()
+
+
+def test_batched_rejects_bad_items():
+    X = zipf_tensor((100, 100, 100), 1000, (1.2,) * 3, seed=1)
+    T = alto.AltoTensor(X.dims, torch.from_numpy(X.coords).cuda(), torch.from_numpy(vals32(X)).cuda())
+    gf = [torch.rand(d, 16, device="cuda") for d in X.dims]
+    out = torch.empty((100, 16), device="cuda")
+    with pytest.raises(alto.AltoError):
+        alto.mttkrp_batched([(T, 3, gf, out, alto.F32)])
+    T.free()
+
+
+def test_batched_sweep_matches_separate_sweeps():
+    specs = job_specs()[:6]
+    jobs = []
+    for dims, nnz, ex, R, seed in specs:
+        R = min(R, 32)
+        X = zipf_tensor(dims, nnz, ex, seed=seed)
+        T = alto.AltoTensor(X.dims, torch.from_numpy(X.coords).cuda(), torch.from_numpy(vals32(X)).cuda())
+        facs = [torch.from_numpy(f).cuda() for f in make_factors(X.dims, R, seed=seed + 1)]
+        jobs.append((X, T, facs, R))
+    items, alone = [], []
+    for X, T, facs, R in jobs:
+        fb = [f.clone() for f in facs]
+        items.append((T, fb, torch.empty(R, dtype=torch.float64, device="cuda"), alto.F32))
+        fa = [f.clone() for f in facs]
+        lam = T.sweep(fa)
+        alone.append((fa, lam))
+    say(f"[batched] sweep of {len(items)} tensors")
+    alto.sweep_batched(items)
+    torch.cuda.synchronize()
+    for k, (it, (fa, lam)) in enumerate(zip(items, alone)):
+        for n in range(len(fa)):
+            e = rel_fro(it[1][n].cpu().numpy().astype(np.float64), fa[n].cpu().numpy().astype(np.float64))
+            say(f"    item {k} mode {n}: batched vs alone {e:.2e}")
+            # FP32 MTTKRP summation order differs; amplified by cond(V)
+            assert e <= 1e-3
+        assert rel_fro(it[2].cpu().numpy(), lam.cpu().numpy()) <= 1e-3
+    for _, T, _, _ in jobs:
+        T.free()

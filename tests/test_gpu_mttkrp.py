@@ -106,7 +106,9 @@ def test_repeat_runs_agree():
     facs = [torch.from_numpy(f).cuda() for f in factors_for(X, 16)]
     a = T.mttkrp(0, facs).cpu().numpy()
     b = T.mttkrp(0, facs).cpu().numpy()
-    assert rel_fro(a.astype(np.float64), b.astype(np.float64)) <= 1e-6
+    # FP32 atomics add in a different order each run; both runs are within
+    # the 1e-5 gate of the exact result, so they agree to 2e-5
+    assert rel_fro(a.astype(np.float64), b.astype(np.float64)) <= 2e-5
 
 
 def test_autotune_records_a_plan_and_stays_exact():
@@ -127,3 +129,31 @@ def test_autotune_records_a_plan_and_stays_exact():
     T2 = alto.AltoTensor(X.dims, coords, vals)
     assert T2.get_plan(2, 16) == T.get_plan(2, 16)
     T2.free()
+
+
+def test_mttkrp_graph_capture_replays_match_eager():
+    """MTTKRP of every mode captured in one HIP graph; each replay, with eager
+    work between replays, matches the eager result."""
+    X, T = built("c2s")
+    facs = [torch.from_numpy(f).cuda() for f in factors_for(X, 16, seed=12)]
+    outs = [torch.empty((d, 16), device="cuda") for d in X.dims]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for n in range(X.nmodes):
+            T.mttkrp(n, facs, out=outs[n])
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for n in range(X.nmodes):
+            T.mttkrp(n, facs, out=outs[n])
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        for n in range(X.nmodes):
+            eager = T.mttkrp(n, facs).cpu().numpy().astype(np.float64)
+            e = rel_fro(outs[n].cpu().numpy().astype(np.float64), eager)
+            say(f"[mttkrp] graph replay {rep} mode {n}: {e:.2e}")
+            assert e <= 2e-5
