@@ -161,12 +161,60 @@ def traffic_from(pmc_dirs, workload, nmodes):
     print(json.dumps(out))
 
 
+def serving_run(njobs, nnz_hi, sweeps, load, budget_gb, max_active, seed=5):
+    """The continuous-batching server on a Poisson stream of CP-ALS jobs.
+    Returns a dict with sweep-latency percentiles and aggregate throughput."""
+    import numpy as np
+    import torch
+
+    from paper_2403_06348_amd import serve
+    from synth.serving import assign_arrivals, job_stream, make_job_tensors
+
+    jobs = job_stream(count=njobs, seed=seed, nnz_hi=nnz_hi)
+    # offered load: `load` x an estimate of the served capacity (MTTKRP-bound
+    # at ~15 GNNZ/s plus ~0.1 ms of R x R work per mode and sweep)
+    demand = sum(sweeps * (j.nnz * len(j.dims) / 15e9 + 1e-4 * len(j.dims)) for j in jobs)
+    rate = load * njobs / demand
+    assign_arrivals(jobs, rate, seed=seed)
+    t = time.perf_counter()
+    data = {j.tag: make_job_tensors(j) for j in jobs}
+    lams = {j.tag: torch.empty(j.rank, dtype=torch.float64, device="cuda") for j in jobs}
+    torch.cuda.synchronize()
+    log(f"[bench] serving: {njobs} jobs, {sum(j.nnz for j in jobs)} nonzeros generated in "
+        f"{time.perf_counter() - t:.1f}s; arrival rate {rate:.1f}/s")
+    S = serve.Server(budget_bytes=int(budget_gb * 2**30), max_active=max_active)
+    t0 = time.perf_counter()
+    for j in jobs:
+        while time.perf_counter() - t0 < j.arrival_s:
+            time.sleep(0.0002)
+        coords, vals, facs = data[j.tag]
+        S.submit(j.tag, j.dims, coords, vals, facs, lams[j.tag], j.rank, sweeps)
+    S.drain()
+    wall = time.perf_counter() - t0
+    done = S.poll(max_records=njobs + 8)
+    st = S.stats()
+    lat = S.sweep_latencies_ms()
+    S.close()
+    turn = np.array([d["done_s"] - d["submit_s"] for d in done]) * 1e3
+    ok = sum(1 for d in done if d["status"] == 0)
+    work = sum(j.nnz * len(j.dims) * sweeps for j in jobs)
+    return {
+        "jobs": njobs, "completed_ok": ok, "sweeps_per_job": sweeps, "arrival_rate_per_s": round(rate, 2),
+        "offered_load": load, "budget_gb": budget_gb, "max_active": max_active, "rounds": st["rounds"],
+        "peak_admitted_gb": round(st["bytes_peak"] / 2**30, 3),
+        "sweep_ms_p50": round(float(np.percentile(lat, 50)), 3), "sweep_ms_p99": round(float(np.percentile(lat, 99)), 3),
+        "job_ms_p50": round(float(np.percentile(turn, 50)), 3), "job_ms_p99": round(float(np.percentile(turn, 99)), 3),
+        "wall_s": round(wall, 3), "gnnz_s": round(work / wall / 1e9, 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--serve-jobs", type=int, default=48, help="jobs in the serving leg of the default run (0: skip)")
     ap.add_argument("--nnz", type=int, default=None, help="override nonzero count (smaller runs)")
     ap.add_argument("--cpu-sample", type=int, default=40_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -195,6 +243,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.config == "c5":
+        res = serving_run(256, 2e7, 10, 0.7, 64.0, 32)
+        print(json.dumps({
+            "metric": METRIC, "value": res["gnnz_s"], "unit": "GNNZ/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": round(res["wall_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "256 CP-ALS jobs, Poisson arrivals at 0.7 x estimated capacity, 3-5 modes, dims "
+                       "log-uniform [1e3,1e6], nnz log-uniform [1e4,2e7], Zipf(1.2), R in {8,16,32}, 10 sweeps "
+                       "each, 64 GiB admission budget"},
+            "serving": res}), flush=True)
+        return
     spec = CONFIGS[args.config]
     rank = spec["rank"]
     fdt = alto.BF16 if spec.get("factor_dtype") == "bf16" else alto.F32
@@ -210,6 +269,7 @@ def main():
     outs = [torch.empty((d, rank), dtype=torch.float32, device="cuda") for d in X.dims]
     lam = torch.empty(rank, dtype=torch.float64, device="cuda")
     nseg = max(1, X.nnz // 4096)
+    nsweeps = int(spec.get("sweeps", 1))
     starts = torch.empty(nseg + 1, dtype=torch.int64, device="cuda")
     if fdt == alto.BF16:
         mfacs = [f.to(torch.bfloat16).view(torch.int16) for f in facs0]
@@ -223,7 +283,8 @@ def main():
             T.mttkrp(n, mfacs, out=outs[n], rank=rank, fdt=fdt, plan=plan)
         for w, f in zip(work, facs0):
             w.copy_(f)
-        T.sweep(work, lam=lam, fdt=fdt)
+        for _ in range(nsweeps):
+            T.sweep(work, lam=lam, fdt=fdt)
         T.free()
 
     if not args.no_autotune and plan is None:
@@ -256,7 +317,7 @@ def main():
     info_words = alto.plan_dims(X.dims)["index_words"]
     fbytes = 2 if fdt == alto.BF16 else 4
     bytes_modes = [algorithmic_bytes(X.dims, X.nnz, rank, info_words, fbytes, n) for n in range(X.nmodes)]
-    mttkrp_per_step = 2 * X.nmodes
+    mttkrp_per_step = (1 + nsweeps) * X.nmodes
     assert launches == mttkrp_per_step * args.steps, (launches, mttkrp_per_step * args.steps)
     avg_launch_ms = kms / launches
     avg_bytes = sum(bytes_modes) / X.nmodes
@@ -282,6 +343,18 @@ def main():
     torch.cuda.synchronize()
     sweep_ms = ev[0].elapsed_time(ev[1])
     plans = [T.get_plan(n, rank, fdt) for n in range(X.nmodes)]
+    f32_per_mode = None
+    if fdt == alto.BF16:
+        # the same MTTKRPs with FP32 factors, for the precision comparison
+        f32_per_mode = []
+        for n in range(X.nmodes):
+            T.autotune(n, facs0, out=outs[n], rank=rank, fdt=alto.F32)
+            ev[0].record()
+            for _ in range(3):
+                T.mttkrp(n, facs0, out=outs[n], rank=rank, fdt=alto.F32)
+            ev[1].record()
+            torch.cuda.synchronize()
+            f32_per_mode.append(ev[0].elapsed_time(ev[1]) / 3)
     T.free()
     torch.cuda.synchronize()
     tb = time.perf_counter()
@@ -306,7 +379,8 @@ def main():
         "dtype": "bf16-factors/f32-accumulate" if fdt == alto.BF16 else "f32",
         "data": "synthetic",
         "config": {
-            "workload": spec["desc"] + "; step = ALTO build + partition + MTTKRP on all modes + one CP-ALS sweep",
+            "workload": spec["desc"] + f"; step = ALTO build + partition + MTTKRP on all modes + {nsweeps} CP-ALS "
+            f"sweep{'s' if nsweeps > 1 else ''}",
             "name": workload,
             "dims": list(X.dims),
             "nnz": X.nnz,
@@ -330,9 +404,18 @@ def main():
             "mttkrp_call_ms_per_mode": [round(x, 4) for x in per_mode],
             "sweep_ms": round(sweep_ms, 3),
             "mttkrp_only_gnnz_s": round(X.nnz * X.nmodes / (sum(per_mode) * 1e-3) / 1e9, 3),
+            "fp32_factor_mttkrp_ms_per_mode": [round(x, 4) for x in f32_per_mode] if f32_per_mode else None,
+            "sweeps_per_step": nsweeps,
             "plans": plans,
         },
     }
+    if args.serve_jobs > 0:
+        del coords, vals
+        torch.cuda.empty_cache()
+        alto.release_cached_memory()
+        out["serving"] = serving_run(args.serve_jobs, 2e6, 10, 0.7, 32.0, 16)
+        out["serving"]["workload"] = ("Poisson stream of 3-5-mode CP-ALS jobs, dims log-uniform [1e3,1e6], nnz "
+                                      "log-uniform [1e4,2e6], Zipf(1.2), R in {8,16,32}, 10 sweeps each")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(X, rank, args.cpu_sample)

@@ -132,8 +132,12 @@ alto_status batched_run(int count, const alto_handle *hs, const int *modes, cons
         const Group &g = kv.second;
         uint64_t nnz = 0;
         for (int j : g.items) nnz += hs[j]->info.nnz;
-        const int ln = nnz > 0 ? (int)std::floor(std::log2((double)nnz)) : -1;
-        const std::array<int, 6> tkey = {g.lpn, g.fdt, g.words, g.maxo, ln, (int)std::min<size_t>(g.items.size(), 64)};
+        // class of the group: kernel variant and the size of an average item
+        // (rounded to a factor of 4), so that a serving round with a slightly
+        // different job mix reuses the plan
+        const double avg = nnz > 0 ? (double)nnz / g.items.size() : 1.0;
+        const int ln = (int)std::floor(std::log2(avg) / 2.0);
+        const std::array<int, 6> tkey = {g.lpn, g.fdt, g.words, g.maxo, ln, 0};
         std::pair<int, int> tuned = {0, 0};
         {
             std::lock_guard<std::mutex> lk(g_btune_mu);
