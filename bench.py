@@ -318,8 +318,10 @@ def main():
     fbytes = 2 if fdt == alto.BF16 else 4
     bytes_modes = [algorithmic_bytes(X.dims, X.nnz, rank, info_words, fbytes, n) for n in range(X.nmodes)]
     mttkrp_per_step = (1 + nsweeps) * X.nmodes
-    assert launches == mttkrp_per_step * args.steps, (launches, mttkrp_per_step * args.steps)
-    avg_launch_ms = kms / launches
+    calls = mttkrp_per_step * args.steps
+    assert launches >= calls, (launches, calls)
+    # one MTTKRP is one launch of the main kernel, or one per rank tile
+    avg_launch_ms = kms / calls
     avg_bytes = sum(bytes_modes) / X.nmodes
     achieved = avg_bytes / (avg_launch_ms * 1e-3) / 1e9
     value = X.nnz * mttkrp_per_step / (ms_per_step * 1e-3) / 1e9
@@ -394,9 +396,11 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_mttkrp (main MTTKRP kernel), average over all launches in the timed region",
+            "kernel": "k_mttkrp (main MTTKRP kernel), per MTTKRP (sum over its rank-tile launches), averaged over "
+            "the timed region",
             "alg_bytes_per_launch": round(avg_bytes),
             "avg_launch_ms": round(avg_launch_ms, 5),
+            "launches_per_mttkrp": round(launches / calls, 3),
             "kernel_sha": kernel_hash(),
         },
         "breakdown": {

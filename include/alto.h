@@ -64,8 +64,12 @@ typedef enum { ALTO_F32 = 0, ALTO_BF16 = 1 } alto_dtype;
  * ALTO_CR_RUN: runs of consecutive nonzeros with the same output row are merged
  *   in registers and added to the output directly (the GPU form of the
  *   output-oriented traversal with atomics only where rows are shared).
+ * ALTO_CR_DIRECT: for short modes, every output row of the mode (one rank tile
+ *   of it) is held in LDS for the workgroup's whole line segment and added to
+ *   the output once at its end (the paper's temporary rows indexed by the mode
+ *   interval, which then spans the whole mode).
  * ALTO_CR_AUTO: chosen per mode from the fiber reuse nnz / dims[mode]. */
-typedef enum { ALTO_CR_AUTO = 0, ALTO_CR_TILE = 1, ALTO_CR_RUN = 2 } alto_conflict;
+typedef enum { ALTO_CR_AUTO = 0, ALTO_CR_TILE = 1, ALTO_CR_RUN = 2, ALTO_CR_DIRECT = 3 } alto_conflict;
 
 /* Where the merged output rows are summed.
  * ALTO_ACC_F64: in an FP64 buffer (handle workspace), rounded once to FP32.
@@ -89,6 +93,7 @@ typedef struct {
     int block_threads;   /* 256, 512 or 1024                                       */
     int table_slots;     /* LDS merge-table rows (power of two), TILE only         */
     int accumulate;      /* alto_accumulate                                        */
+    int rank_tile;       /* columns per pass (multiple of 4 dividing rank; 0: all) */
 } alto_mttkrp_plan;
 
 /* Host-side description of a handle (see alto_info). */

@@ -13,12 +13,12 @@ import ctypes
 
 from . import _capi
 from ._capi import (  # noqa: F401
-    ACC_DEFAULT, ACC_F32, ACC_F64, ACC_XCD_F32, ACC_XCD_F64, BF16, CR_AUTO, CR_RUN, CR_TILE, F32, MttkrpPlan, STATUS_NAMES,
+    ACC_DEFAULT, ACC_F32, ACC_F64, ACC_XCD_F32, ACC_XCD_F64, BF16, CR_AUTO, CR_DIRECT, CR_RUN, CR_TILE, F32, MttkrpPlan, STATUS_NAMES,
 )
 
 __all__ = [
     "AltoError", "AltoTensor", "plan_dims", "plan_decode_host", "mttkrp_batched", "version", "F32", "BF16",
-    "CR_AUTO", "CR_TILE", "CR_RUN", "ACC_DEFAULT", "ACC_F64", "ACC_F32", "ACC_XCD_F32", "ACC_XCD_F64",
+    "CR_AUTO", "CR_TILE", "CR_RUN", "CR_DIRECT", "ACC_DEFAULT", "ACC_F64", "ACC_F32", "ACC_XCD_F32", "ACC_XCD_F64",
 ]
 
 

@@ -32,6 +32,7 @@ BF16 = 1
 CR_AUTO = 0
 CR_TILE = 1
 CR_RUN = 2
+CR_DIRECT = 3
 
 ACC_DEFAULT = 0
 ACC_F64 = 1
@@ -47,6 +48,7 @@ class MttkrpPlan(ctypes.Structure):
         ("block_threads", ctypes.c_int),
         ("table_slots", ctypes.c_int),
         ("accumulate", ctypes.c_int),
+        ("rank_tile", ctypes.c_int),
     ]
 
     def as_dict(self):

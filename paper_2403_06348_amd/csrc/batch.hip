@@ -48,6 +48,7 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
         alto_tensor *h = hs[j];
         alto_mttkrp_plan p = default_plan(h, modes[j], ranks[j], g.fdt);
         p.conflict = ALTO_CR_TILE;
+        p.rank_tile = 0;
         p.accumulate = ALTO_ACC_F32;
         p.tile_nnz = tile;
         p.table_slots = std::max(16, p.table_slots * slots_factor / 2);
@@ -200,14 +201,42 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
     const alto_mttkrp_plan base = default_plan(h, mode, rank, fdt);
     std::vector<alto_mttkrp_plan> cands;
     const uint64_t nnz = h->info.nnz;
-    for (int tile : {2048, 4096, 8192, 16384, 32768}) {
-        if (nnz > 0 && (uint64_t)tile * 64 > nnz && tile != base.tile_nnz) continue;  // keep >= 64 tiles
-        for (int f : {1, 2, 4}) {
+    for (int threads : {256, 512}) {
+        for (int tile : {2048, 4096, 8192, 16384, 32768}) {
+            if (nnz > 0 && (uint64_t)tile * 64 > nnz && tile != base.tile_nnz) continue;  // keep >= 64 tiles
+            for (int f : {1, 2, 4}) {
+                alto_mttkrp_plan p = base;
+                p.conflict = ALTO_CR_TILE;
+                p.rank_tile = 0;
+                p.block_threads = threads;
+                p.tile_nnz = tile;
+                p.table_slots = std::max(64, base.table_slots * f / 2);
+                if ((size_t)p.table_slots * (rank + 2) * 4 > 96 * 1024) continue;
+                cands.push_back(p);
+            }
+        }
+    }
+    // rank tiles for the table merge at high rank
+    for (int rt : {rank / 2, rank / 4}) {
+        if (rt < 8 || rt % 4 || rank % rt) continue;
+        for (int tile : {4096, 16384}) {
             alto_mttkrp_plan p = base;
             p.conflict = ALTO_CR_TILE;
             p.tile_nnz = tile;
-            p.table_slots = std::max(64, base.table_slots * f / 2);
-            if ((size_t)p.table_slots * (rank + 2) * 4 > 96 * 1024) continue;
+            p.rank_tile = rt;
+            p.table_slots = std::max(64, pow2_floor(8192 / rt));
+            cands.push_back(p);
+        }
+    }
+    // the whole mode in LDS, for short modes
+    for (int rt = rank; rt >= 4; rt /= 2) {
+        if (rt % 4 || rank % rt) break;
+        if ((size_t)h->info.dims[mode] * (rt + 1) * 4 > kDirectLdsBytes) continue;
+        for (int threads : {256, 512}) {
+            alto_mttkrp_plan p = base;
+            p.conflict = ALTO_CR_DIRECT;
+            p.rank_tile = rt == rank ? 0 : rt;
+            p.block_threads = threads;
             cands.push_back(p);
         }
     }

@@ -62,7 +62,7 @@ template <int WORDS>
 struct RsCfg;
 template <>
 struct RsCfg<1> {
-    static constexpr int IPT = 16;
+    static constexpr int IPT = 8;
 };
 template <>
 struct RsCfg<2> {

@@ -10,6 +10,7 @@ constexpr int kMaxProbe = 16;       // LDS table probes before falling back to t
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr uint32_t kHotHits = 4;    // runs merged in one tile that make a row stay in LDS
 constexpr int kKeepTiles = 16;      // tiles a row may stay in LDS before it is flushed
+constexpr size_t kDirectLdsBytes = 128 * 1024;  // largest whole-mode LDS accumulator
 
 struct MttkrpArgs {
     LinePlan lp;
@@ -26,12 +27,14 @@ struct MttkrpArgs {
     uint64_t ntiles;
     uint64_t tq, tr;  // nnz / ntiles, nnz % ntiles
     int mode, rank, nmodes;
-    int tile_merge;   // 1: LDS table merge, 0: direct atomics
+    int tile_merge;   // 0: direct atomics, 1: LDS table merge, 2: whole mode in LDS
     int use64;        // 1: accumulate into out64
     int slots_log2;
     int rec;          // staged record length (u32) per nonzero
     int xcd_map;      // 1: contiguous tile ranges per XCD
     int copies;       // private output copies, indexed by XCD id (1: shared output)
+    uint32_t ld;      // row stride of factors and output (the full rank)
+    uint32_t col0;    // first column of this rank tile
     uint64_t copy_stride;  // elements per copy
 };
 
@@ -47,9 +50,11 @@ alto_status ensure_ws(void **p, size_t *have, size_t need);
 alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
                        const alto_mttkrp_plan &p, hipStream_t s);
 void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
-               const alto_mttkrp_plan &p, float *out32, double *out64, MttkrpArgs *a);
+               const alto_mttkrp_plan &p, float *out32, double *out64, MttkrpArgs *a, int col0 = 0,
+               int rank_tile = 0);
 size_t lds_bytes(const MttkrpArgs &a, int threads);
 int lpn_for(int rank);
+int pow2_floor(int v);
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s);
 const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch);
 const void *zero_outputs_kernel();

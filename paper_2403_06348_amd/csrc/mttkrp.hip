@@ -95,7 +95,7 @@ __device__ inline float4 bload4<uint16_t>(__amdgpu_buffer_rsrc_t r, uint32_t byt
 __device__ inline uint32_t xcd_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 15u; }
 
 __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, const float *acc) {
-    uint64_t o = (uint64_t)row * a.rank + r0;
+    uint64_t o = (uint64_t)row * a.ld + a.col0 + r0;
     if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
     if (a.use64) {
 #pragma unroll
@@ -149,11 +149,12 @@ __device__ inline void flush_run(const MttkrpArgs &a, float *tval, uint32_t *thi
                                  const float *acc) {
     if (dst & kSlotBit) {
         const uint32_t slot = dst & ~kSlotBit;
-        float *t = tval + (uint64_t)slot * a.rank + r0;
+        float *t = tval + (uint64_t)slot * (a.rank + 1) + r0;
 #pragma unroll
         for (int j = 0; j < 4; j++)
             if (r0 + j < a.rank) __hip_atomic_fetch_add(t + j, acc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (q == 0) __hip_atomic_fetch_add(thits + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (q == 0 && a.tile_merge == 1)
+            __hip_atomic_fetch_add(thits + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
         global_add(a, dst, r0, acc);
     }
@@ -174,11 +175,16 @@ template <int LPN, typename FT, int WORDS, int MAXO>
 __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep, uint64_t t0, uint64_t t1) {
     // nonzeros gathered together per group
     constexpr int SB = MAXO == 2 ? (LPN < 4 ? LPN : 4) : (LPN < 2 ? LPN : 2);
-    const int S = a.tile_merge ? (1 << a.slots_log2) : 0;
+    // table rows: hashed slots (tile merge) or every row of the mode (direct).
+    // Rows are rank + 1 floats apart: the odd stride spreads the rows the
+    // groups of a wave update at once over all LDS banks.
+    const int S = a.tile_merge == 1 ? (1 << a.slots_log2) : (a.tile_merge == 2 ? (int)a.dim_out : 0);
+    const int SK = a.tile_merge == 1 ? S : 0;  // key / hit arrays
+    const int TS = a.rank + 1;
     uint32_t *tkey = smem;
-    uint32_t *thits = smem + S;
-    float *tval = (float *)(smem + 2 * S);
-    uint32_t *stage = smem + 2 * S + (size_t)S * a.rank;
+    uint32_t *thits = smem + SK;
+    float *tval = (float *)(smem + 2 * SK);
+    uint32_t *stage = smem + ((2 * SK + (size_t)S * TS + 3) & ~(size_t)3);
     const int REC = a.rec;  // [val, destination, other coordinates...], multiple of 4
     const int tid = threadIdx.x;
     const int q = tid & (LPN - 1);
@@ -190,11 +196,11 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
     const int nother = a.nmodes - 1;
 
     if (a.tile_merge) {
-        for (int i = tid; i < S; i += blockDim.x) {
+        for (int i = tid; i < SK; i += blockDim.x) {
             tkey[i] = kEmptyRow;
             thits[i] = 0;
         }
-        for (int i = tid; i < S * a.rank; i += blockDim.x) tval[i] = 0.f;
+        for (int i = tid; i < S * TS; i += blockDim.x) tval[i] = 0.f;
         __syncthreads();
     }
 
@@ -245,20 +251,22 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
                 uint32_t dst = kEmptyRow;
                 if (row_ok) {
                     dst = row;
-                    if (a.tile_merge) {
+                    if (a.tile_merge == 1) {
                         const uint32_t slot = table_slot(tkey, row, a.slots_log2);
                         if (slot != kNoSlot) dst = kSlotBit | slot;
+                    } else if (a.tile_merge == 2) {
+                        dst = kSlotBit | row;
                     }
                 }
-                rec[0] = row_ok ? __float_as_uint(val) : 0u;
-                rec[1] = dst;
                 if (MAXO == 2 && WORDS == 1) {
-                    // up to 3 modes: the masks stay in scalar registers
+                    // up to 3 modes: the masks stay in scalar registers, and
+                    // the record is one 16-byte LDS store
                     const uint32_t o0 = a.mode == 0 ? c3[1] : c3[0];
                     const uint32_t o1 = a.mode == 2 ? c3[1] : c3[2];
-                    rec[2] = o0;
-                    rec[3] = o1;
+                    *(uint4 *)rec = make_uint4(row_ok ? __float_as_uint(val) : 0u, dst, o0, o1);
                 } else {
+                    rec[0] = row_ok ? __float_as_uint(val) : 0u;
+                    rec[1] = dst;
                     // modes in a rolled loop: each mode's masks are fetched
                     // into scalar registers when needed instead of all at once
                     int k = 2;
@@ -270,6 +278,8 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
                         }
                     }
                 }
+            } else if (MAXO == 2 && WORDS == 1) {
+                *(uint4 *)rec = make_uint4(0u, kEmptyRow, 0u, 0u);
             } else {
                 rec[0] = 0u;
                 rec[1] = kEmptyRow;
@@ -306,14 +316,14 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
 #pragma unroll
                                 for (int s = 0; s < SB; s++) {
                                     const uint32_t idx = rec_coord(head[s], head2[s], k);
-                                    g[k][s] = bload4<FT>(rs, (idx * (uint32_t)a.rank + (uint32_t)r0) * (uint32_t)sizeof(FT));
+                                    g[k][s] = bload4<FT>(rs, (idx * a.ld + a.col0 + (uint32_t)r0) * (uint32_t)sizeof(FT));
                                 }
                             } else {
                                 const void *f = a.fac_other[k];
 #pragma unroll
                                 for (int s = 0; s < SB; s++) {
                                     const uint32_t idx = min(rec_coord(head[s], head2[s], k), a.last_other[k]);
-                                    g[k][s] = ract ? load4<FT>(f, (uint64_t)idx * a.rank + r0)
+                                    g[k][s] = ract ? load4<FT>(f, (uint64_t)idx * a.ld + a.col0 + r0)
                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
                                 }
                             }
@@ -337,7 +347,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
 #pragma unroll
                         for (int s = 0; s < SB; s++) {
                             const uint32_t idx = min(gst[(sb + s) * REC + 2 + k], a.last_other[k]);
-                            const float4 g = ract ? load4<FT>(f, (uint64_t)idx * a.rank + r0)
+                            const float4 g = ract ? load4<FT>(f, (uint64_t)idx * a.ld + a.col0 + r0)
                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
                             p[s][0] *= g.x;
                             p[s][1] *= g.y;
@@ -366,7 +376,19 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
         }
         if (cur != kEmptyRow) flush_run(a, tval, thits, cur, q, r0, acc);
 
-        if (a.tile_merge) {
+        if (a.tile_merge == 2 && t + 1 == t1) {
+            // ---- end of the stretch: every row of the mode held in LDS is
+            // added to the output once
+            __syncthreads();
+            const int qr = a.rank >> 2;
+            for (int i = tid; i < S * qr; i += blockDim.x) {
+                const int row = i / qr, part = i - row * qr;
+                const float *tv = tval + (size_t)row * TS + part * 4;
+                const float vv[4] = {tv[0], tv[1], tv[2], tv[3]};
+                if (vv[0] != 0.f || vv[1] != 0.f || vv[2] != 0.f || vv[3] != 0.f) global_add(a, (uint32_t)row, part * 4, vv);
+            }
+            __syncthreads();
+        } else if (a.tile_merge == 1) {
             // ---- tile end: rows merged many times in this tile (high reuse)
             // stay in LDS for the next tile; the others are added to the
             // output and their slots cleared.  Everything is flushed every
@@ -386,11 +408,13 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             for (int i = tid; i < S * qr; i += blockDim.x) {
                 const int slot = i / qr, part = i - slot * qr;
                 if (thits[slot] == kFlushMark) {
-                    float *tv = tval + (size_t)slot * a.rank + part * 4;
-                    const float4 v = *(const float4 *)tv;
-                    const float vv[4] = {v.x, v.y, v.z, v.w};
+                    float *tv = tval + (size_t)slot * TS + part * 4;
+                    const float vv[4] = {tv[0], tv[1], tv[2], tv[3]};
                     global_add(a, tkey[slot], part * 4, vv);
-                    *(float4 *)tv = make_float4(0.f, 0.f, 0.f, 0.f);
+                    tv[0] = 0.f;
+                    tv[1] = 0.f;
+                    tv[2] = 0.f;
+                    tv[3] = 0.f;
                 }
             }
             __syncthreads();
@@ -418,7 +442,7 @@ __device__ inline void stretch_of(uint64_t total, int xcd_map, uint64_t *g0, uin
 // Kernel variants: MAXO = most other modes handled with fully unrolled
 // gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
 template <int LPN, typename FT, int WORDS, int MAXO>
-__global__ __launch_bounds__(256) void k_mttkrp(const MttkrpArgs a) {
+__global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ uint32_t nkeep;
     uint64_t t0, t1;
@@ -532,6 +556,12 @@ DevProps &props(int dev) {
 
 }  // namespace
 
+int pow2_floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
 int lpn_for(int rank) {
     int l = 1;
     while (4 * l < rank) l <<= 1;
@@ -557,6 +587,20 @@ alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt)
     while (tile < 16384 && tile * 8192 < h->info.nnz) tile *= 2;
     p.tile_nnz = (int)tile;
     p.accumulate = ALTO_ACC_F32;
+    // a mode short enough to hold whole in LDS (with a rank tile of at least
+    // 8 columns) is accumulated there for the workgroup's whole segment
+    for (int rt = rank; rt >= 8 && rt % 4 == 0; rt /= 2) {
+        if (rank % rt) break;
+        const size_t bytes = (size_t)h->info.dims[mode] * (rt + 1) * 4;
+        if (bytes <= kDirectLdsBytes && reuse > 4.0) {
+            p.conflict = ALTO_CR_DIRECT;
+            p.rank_tile = rt == rank ? 0 : rt;
+            // one workgroup per CU when the table takes most of the LDS:
+            // give it more waves
+            if (bytes > kDirectLdsBytes / 2) p.block_threads = 512;
+            break;
+        }
+    }
     (void)fdt;
     return p;
 }
@@ -593,20 +637,30 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
     if (ri >= 0 && ri <= 32 && h->has_tuned[mode][fdt][ri]) p = h->tuned[mode][fdt][ri];
     else if (ri >= 0 && ri <= 32) cached_tuned(h, mode, rank, fdt, &p);
     if (in) {
-        if (in->conflict) p.conflict = in->conflict;
+        if (in->conflict) {
+            p.conflict = in->conflict;
+            p.rank_tile = 0;
+        }
+        if (in->rank_tile) p.rank_tile = in->rank_tile;
         if (in->tile_nnz) p.tile_nnz = in->tile_nnz;
         if (in->block_threads) p.block_threads = in->block_threads;
         if (in->table_slots) p.table_slots = in->table_slots;
         if (in->accumulate) p.accumulate = in->accumulate;
     }
     if (p.accumulate < ALTO_ACC_F64 || p.accumulate > ALTO_ACC_XCD_F64) return fail(ALTO_ERR_ARG, "bad accumulate mode");
-    if (p.conflict != ALTO_CR_TILE && p.conflict != ALTO_CR_RUN) return fail(ALTO_ERR_ARG, "bad conflict mode");
-    if (p.block_threads != 256) return fail(ALTO_ERR_ARG, "block_threads must be 256");
+    if (p.conflict != ALTO_CR_TILE && p.conflict != ALTO_CR_RUN && p.conflict != ALTO_CR_DIRECT)
+        return fail(ALTO_ERR_ARG, "bad conflict mode");
+    if (p.rank_tile < 0 || p.rank_tile % 4 || (p.rank_tile > 0 && rank % p.rank_tile))
+        return fail(ALTO_ERR_ARG, "rank_tile must be a multiple of 4 dividing rank");
+    const int rt = p.rank_tile > 0 ? p.rank_tile : rank;
+    if (p.conflict == ALTO_CR_DIRECT && (size_t)h->info.dims[mode] * (rt + 1) * 4 > kDirectLdsBytes)
+        return fail(ALTO_ERR_ARG, "mode too long to hold in LDS for this rank tile");
+    if (p.block_threads != 256 && p.block_threads != 512) return fail(ALTO_ERR_ARG, "block_threads must be 256 or 512");
     if (p.tile_nnz < 1) return fail(ALTO_ERR_ARG, "tile_nnz must be positive");
     if (p.conflict == ALTO_CR_TILE) {
         if (p.table_slots < 16 || (p.table_slots & (p.table_slots - 1)))
             return fail(ALTO_ERR_ARG, "table_slots must be a power of two >= 16");
-        const size_t lds = (size_t)p.table_slots * (rank + 1) * 4;
+        const size_t lds = (size_t)p.table_slots * (rt + 2) * 4;
         if (lds > 96 * 1024) return fail(ALTO_ERR_ARG, "LDS table too large for rank");
     }
     *out = p;
@@ -645,7 +699,7 @@ alto_status ensure_ws(void **p, size_t *have, size_t need) {
 }
 
 void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
-               const alto_mttkrp_plan &p, float *out32, double *out64, MttkrpArgs *a) {
+               const alto_mttkrp_plan &p, float *out32, double *out64, MttkrpArgs *a, int col0, int rank_tile) {
     memset(a, 0, sizeof(*a));
     a->lp = h->lp;
     int k = 0;
@@ -676,9 +730,11 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
     a->tq = h->info.nnz / L;
     a->tr = h->info.nnz % L;
     a->mode = mode;
-    a->rank = rank;
+    a->rank = rank_tile > 0 ? rank_tile : rank;
+    a->ld = (uint32_t)rank;
+    a->col0 = (uint32_t)col0;
     a->nmodes = h->info.nmodes;
-    a->tile_merge = p.conflict == ALTO_CR_TILE ? 1 : 0;
+    a->tile_merge = p.conflict == ALTO_CR_TILE ? 1 : (p.conflict == ALTO_CR_DIRECT ? 2 : 0);
     a->use64 = (p.accumulate == ALTO_ACC_F64 || p.accumulate == ALTO_ACC_XCD_F64) ? 1 : 0;
     a->copies = (p.accumulate == ALTO_ACC_XCD_F32 || p.accumulate == ALTO_ACC_XCD_F64) ? kXcdCopies : 1;
     a->copy_stride = h->info.dims[mode] * (uint64_t)rank;
@@ -689,8 +745,9 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
 }
 
 size_t lds_bytes(const MttkrpArgs &a, int threads) {
-    const size_t S = a.tile_merge ? ((size_t)1 << a.slots_log2) : 0;
-    return (2 * S + S * a.rank) * 4 + (size_t)threads * a.rec * 4;
+    const size_t S = a.tile_merge == 1 ? ((size_t)1 << a.slots_log2) : (a.tile_merge == 2 ? a.dim_out : 0);
+    const size_t SK = a.tile_merge == 1 ? S : 0;
+    return ((2 * SK + S * (a.rank + 1) + 3) & ~(size_t)3) * 4 + (size_t)threads * a.rec * 4;
 }
 
 // ---- optional per-launch timing with HIP events
@@ -798,10 +855,14 @@ alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *
     }
     ALTO_HIP(hipGetLastError());
     if (h->info.nnz > 0) {
-        MttkrpArgs a;
-        fill_args(h, mode, rank, fdt, factors, p, acc32, out64, &a);
-        alto_status st = launch_mttkrp(h, fdt, a, p.block_threads, s);
-        if (st != ALTO_OK) return st;
+        // one launch per rank tile (columns [c, c + rt) of factors and output)
+        const int rt = p.rank_tile > 0 ? p.rank_tile : rank;
+        for (int c = 0; c < rank; c += rt) {
+            MttkrpArgs a;
+            fill_args(h, mode, rank, fdt, factors, p, acc32, out64, &a, c, rt);
+            alto_status st = launch_mttkrp(h, fdt, a, p.block_threads, s);
+            if (st != ALTO_OK) return st;
+        }
     }
     if (!direct) {
         const unsigned g1 = grid_for(nout, 256, 16384);

@@ -157,3 +157,35 @@ def test_mttkrp_graph_capture_replays_match_eager():
             e = rel_fro(outs[n].cpu().numpy().astype(np.float64), eager)
             say(f"[mttkrp] graph replay {rep} mode {n}: {e:.2e}")
             assert e <= 2e-5
+
+
+@pytest.mark.parametrize("name,rank,mode,plan", [
+    ("c3s", 32, 1, dict(conflict=alto.CR_DIRECT, rank_tile=8)),
+    ("c3s", 32, 2, dict(conflict=alto.CR_DIRECT, rank_tile=16)),
+    ("c3s", 32, 2, dict(conflict=alto.CR_DIRECT, rank_tile=16, block_threads=512)),
+    ("unit", 20, 0, dict(conflict=alto.CR_DIRECT)),
+    ("unit", 20, 2, dict(conflict=alto.CR_DIRECT)),
+    ("c1", 8, 1, dict(conflict=alto.CR_DIRECT, rank_tile=4)),
+    ("c2s", 32, 0, dict(conflict=alto.CR_TILE, rank_tile=8)),
+    ("c2s", 64, 2, dict(conflict=alto.CR_TILE, rank_tile=16, tile_nnz=4096)),
+    ("c2s", 64, 1, dict(conflict=alto.CR_RUN, rank_tile=32)),
+])
+def test_mttkrp_whole_mode_lds_and_rank_tiles(name, rank, mode, plan):
+    X, T = built(name)
+    facs = factors_for(X, rank, seed=rank + 1)
+    ref = oracle_modes(X, facs)[mode]
+    gf = [torch.from_numpy(f).cuda() for f in facs]
+    say(f"[mttkrp] {name} R={rank} mode={mode} plan={plan}")
+    got = T.mttkrp(mode, gf, plan=plan).cpu().numpy().astype(np.float64)
+    e = rel_fro(got, ref)
+    say(f"    rel err {e:.3e}")
+    assert e <= TOL
+
+
+def test_whole_mode_lds_rejects_long_modes():
+    X, T = built("c2s")
+    gf = [torch.rand(d, 16, device="cuda") for d in X.dims]
+    with pytest.raises(alto.AltoError):
+        T.mttkrp(0, gf, plan=dict(conflict=alto.CR_DIRECT))
+    with pytest.raises(alto.AltoError):
+        T.mttkrp(0, gf, plan=dict(rank_tile=12))
