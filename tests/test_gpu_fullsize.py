@@ -1,0 +1,70 @@
+"""Parity at the full workload sizes, in the launch configuration the bench
+times (autotuned plans): the ordered ALTO tensor bit for bit, and MTTKRP on
+sampled output rows (the heaviest rows and random ones), which the oracle
+computes one by one in a single pass over the nonzeros."""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_cases import rel_fro, say, vals32
+from synth import CONFIGS, make_config, make_factors
+
+pytestmark = pytest.mark.gpu
+
+alto = pytest.importorskip("paper_2403_06348_amd")
+torch = pytest.importorskip("torch")
+
+_cache = {}
+
+
+def full(name):
+    if name not in _cache:
+        say(f"[full] generating {name}")
+        X = make_config(name)
+        coords = torch.from_numpy(X.coords).cuda()
+        vals = torch.from_numpy(vals32(X)).cuda()
+        T = alto.AltoTensor(X.dims, coords, vals)
+        del coords, vals
+        _cache[name] = (X, T)
+    return _cache[name]
+
+
+def sample_rows(coords_n, dim, k_heavy=16, k_rand=200, seed=0):
+    counts = np.bincount(coords_n, minlength=dim)
+    heavy = np.argsort(counts)[::-1][:k_heavy]
+    rnd = np.random.default_rng(seed).choice(dim, size=min(k_rand, dim), replace=False)
+    return np.unique(np.concatenate([heavy, rnd]))
+
+
+def test_full_c2_ordered_tensor_bitexact():
+    X, T = full("c2")
+    say("[full] c2 keys and values")
+    keys, vals = T.export()
+    torch.cuda.synchronize()
+    ok = oracle.encode(X.dims, X.coords)[:, 0]
+    perm = np.argsort(ok, kind="stable")
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64)[:, 0], ok[perm])
+    np.testing.assert_array_equal(vals.cpu().numpy(), vals32(X)[perm])
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_full_mttkrp_sampled_rows(name):
+    X, T = full(name)
+    R = CONFIGS[name]["rank"]
+    facs = make_factors(X.dims, R, seed=7)
+    gf = [torch.from_numpy(f).cuda() for f in facs]
+    v64 = vals32(X).astype(np.float64)
+    f64 = [f.astype(np.float64) for f in facs]
+    for n in range(X.nmodes):
+        out = torch.empty((X.dims[n], R), device="cuda")
+        plan = T.autotune(n, gf, out=out)
+        say(f"[full] {name} mode {n} plan {plan}")
+        got = T.mttkrp(n, gf, out=out).cpu().numpy().astype(np.float64)
+        rows = sample_rows(X.coords[n], X.dims[n], seed=n)
+        ref = oracle.mttkrp_rows(X.dims, X.coords, v64, f64, n, rows)
+        e = rel_fro(got[rows], ref)
+        worst = max(rel_fro(got[r], ref[i]) for i, r in enumerate(rows) if np.any(ref[i]))
+        say(f"    {len(rows)} rows: rel err {e:.2e}, worst row {worst:.2e}")
+        assert e <= 1e-5
+        assert worst <= 1e-4
