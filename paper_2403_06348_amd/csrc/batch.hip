@@ -52,6 +52,10 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
         p.accumulate = ALTO_ACC_F32;
         p.tile_nnz = tile;
         p.table_slots = std::max(16, p.table_slots * slots_factor / 2);
+        // one LDS size serves the whole launch: keep every table within
+        // 96 KiB of FP64 rows, keys and hit counts
+        while (p.table_slots > 16 && (size_t)p.table_slots * (2 * (ranks[j] + 1) + 2) * 4 > 96 * 1024)
+            p.table_slots /= 2;
         fill_args(h, modes[j], ranks[j], g.fdt, factors[j], p, outs[j], nullptr, &jobs[k]);
         jobs[k].xcd_map = 0;
         const uint64_t tiles = h->info.nnz == 0 ? 0 : jobs[k].ntiles;
@@ -211,7 +215,7 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
                 p.block_threads = threads;
                 p.tile_nnz = tile;
                 p.table_slots = std::max(64, base.table_slots * f / 2);
-                if ((size_t)p.table_slots * (rank + 2) * 4 > 96 * 1024) continue;
+                if ((size_t)p.table_slots * (2 * rank + 4) * 4 > 144 * 1024) continue;
                 cands.push_back(p);
             }
         }
@@ -231,8 +235,8 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
     // the whole mode in LDS, for short modes
     for (int rt = rank; rt >= 4; rt /= 2) {
         if (rt % 4 || rank % rt) break;
-        if ((size_t)h->info.dims[mode] * (rt + 1) * 4 > kDirectLdsBytes) continue;
         for (int threads : {256, 512}) {
+            if ((size_t)h->info.dims[mode] * (rt + 1) * 8 > direct_table_limit(h, threads)) continue;
             alto_mttkrp_plan p = base;
             p.conflict = ALTO_CR_DIRECT;
             p.rank_tile = rt == rank ? 0 : rt;

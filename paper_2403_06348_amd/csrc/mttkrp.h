@@ -10,7 +10,6 @@ constexpr int kMaxProbe = 16;       // LDS table probes before falling back to t
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr uint32_t kHotHits = 4;    // runs merged in one tile that make a row stay in LDS
 constexpr int kKeepTiles = 16;      // tiles a row may stay in LDS before it is flushed
-constexpr size_t kDirectLdsBytes = 128 * 1024;  // largest whole-mode LDS accumulator
 
 struct MttkrpArgs {
     LinePlan lp;
@@ -57,6 +56,10 @@ int lpn_for(int rank);
 int pow2_floor(int v);
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s);
 const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch);
+const void *pick_single(int lpn, int fdt, int words, const MttkrpArgs &a);
+// Largest whole-mode LDS table (bytes) a workgroup of `threads` can hold
+// beside its record staging on this tensor's device.
+size_t direct_table_limit(const alto_tensor *h, int threads);
 const void *zero_outputs_kernel();
 int device_cus(int dev);
 

@@ -94,8 +94,18 @@ __device__ inline float4 bload4<uint16_t>(__amdgpu_buffer_rsrc_t r, uint32_t byt
 // Hardware id of the XCD (accelerator complex die) running this wave.
 __device__ inline uint32_t xcd_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 15u; }
 
-__device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, const float *acc) {
+// Add 4 columns of partial sums (FP32 run sums or FP64 LDS rows) to the
+// output row, or to this XCD's copy of it.
+// FAST: the plan is known to add FP32 straight into the output.
+template <bool FAST = false, typename T>
+__device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, const T *acc) {
     uint64_t o = (uint64_t)row * a.ld + a.col0 + r0;
+    if (FAST) {
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (r0 + j < a.rank) unsafeAtomicAdd(a.out32 + o + j, (float)acc[j]);
+        return;
+    }
     if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
     if (a.use64) {
 #pragma unroll
@@ -104,38 +114,34 @@ __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, con
     } else {
 #pragma unroll
         for (int j = 0; j < 4; j++)
-            if (r0 + j < a.rank) unsafeAtomicAdd(a.out32 + o + j, acc[j]);
+            if (r0 + j < a.rank) unsafeAtomicAdd(a.out32 + o + j, (float)acc[j]);
     }
 }
 
 // Slot of `row` in the LDS table of partial rows, inserting it if absent.
-// The table is bucketized: a row may live in one of the 4 slots of its
-// bucket (read with a single 16-byte LDS load) or of a second bucket, so a
-// lookup costs one or two LDS reads and never a long probe sequence.
-// kNoSlot when both buckets are full: the caller then adds to the output
-// directly.  A row may own two slots (after an eviction broke its lookup);
-// both are added to the output, so this only costs merging, never
-// correctness.
+// The table is bucketized: a row lives in one of the 4 slots of its bucket,
+// read with a single 16-byte LDS load; an absent row takes the first empty
+// slot with one compare-and-swap.  kNoSlot when the bucket is full or the
+// swap lost a race: the caller then adds to the output directly.  A row may
+// own two slots of its bucket (after an eviction, or two racing inserts);
+// every slot is added to the output with its own key, so this only costs
+// merging, never correctness.  One read and at most one swap keep the
+// lookup's chain of dependent LDS round trips short.
 __device__ inline uint32_t table_slot(uint32_t *tkey, uint32_t row, int log2s) {
-    const uint32_t bmask = (1u << (log2s - 2)) - 1;
-    const uint32_t b1 = row_hash(row, log2s - 2) & bmask;
-    const uint32_t b2 = (row_hash(row ^ 0x5bd1e995u, log2s - 2) ^ 1u) & bmask;
+    const uint32_t b = row_hash(row, log2s - 2) & ((1u << (log2s - 2)) - 1);
+    uint32_t *bk = tkey + 4 * b;
+    const uint4 k4 = *(const uint4 *)bk;
+    const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w};
 #pragma unroll
-    for (int pass = 0; pass < 2; pass++) {
-        const uint32_t b = pass == 0 ? b1 : b2;
-        uint32_t *bk = tkey + 4 * b;
-        uint4 k4 = *(const uint4 *)bk;
-        const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w};
+    for (int j = 0; j < 4; j++)
+        if (kk[j] == row) return 4 * b + j;
+    int e = -1;
 #pragma unroll
-        for (int j = 0; j < 4; j++)
-            if (kk[j] == row) return 4 * b + j;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            if (kk[j] == kEmptyRow) {
-                const uint32_t old = atomicCAS(bk + j, kEmptyRow, row);
-                if (old == kEmptyRow || old == row) return 4 * b + j;
-            }
-        }
+    for (int j = 3; j >= 0; j--)
+        if (kk[j] == kEmptyRow) e = j;
+    if (e >= 0) {
+        const uint32_t old = atomicCAS(bk + e, kEmptyRow, row);
+        if (old == kEmptyRow || old == row) return 4 * b + e;
     }
     return kNoSlot;
 }
@@ -144,19 +150,23 @@ __device__ inline uint32_t table_slot(uint32_t *tkey, uint32_t row, int log2s) {
 // an LDS slot, else the output row itself (rows are below 2^31).
 constexpr uint32_t kSlotBit = 0x80000000u;
 
-// Add a finished run of updates to its destination.
-__device__ inline void flush_run(const MttkrpArgs &a, float *tval, uint32_t *thits, uint32_t dst, int q, int r0,
+// Add a finished run of updates to its destination.  LDS rows are FP64:
+// besides the precision, gfx950's LDS adds FP64 atomically about twenty
+// times faster than FP32 (ds_add_f64 against ds_add_f32).
+template <int TM, bool FAST>
+__device__ inline void flush_run(const MttkrpArgs &a, double *tval, uint32_t *thits, uint32_t dst, int q, int r0,
                                  const float *acc) {
     if (dst & kSlotBit) {
         const uint32_t slot = dst & ~kSlotBit;
-        float *t = tval + (uint64_t)slot * (a.rank + 1) + r0;
+        double *t = tval + (uint64_t)slot * (a.rank + 1) + r0;
 #pragma unroll
         for (int j = 0; j < 4; j++)
-            if (r0 + j < a.rank) __hip_atomic_fetch_add(t + j, acc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (q == 0 && a.tile_merge == 1)
+            if (r0 + j < a.rank)
+                __hip_atomic_fetch_add(t + j, (double)acc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (q == 0 && (TM >= 0 ? TM : a.tile_merge) == 1)
             __hip_atomic_fetch_add(thits + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
-        global_add(a, dst, r0, acc);
+        global_add<FAST>(a, dst, r0, acc);
     }
 }
 
@@ -169,22 +179,41 @@ __device__ inline uint32_t rec_coord(const uint4 &h, const uint4 &h2, int k) {
 
 // Kernel variants: MAXO = most other modes handled with fully unrolled
 // gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
+// Compress one 64-bit index word with masks read from LDS (every lane reads
+// the same address: a broadcast).
+__device__ inline uint64_t compress_lds(uint64_t x, const uint64_t *m) {
+    x &= m[0];
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        const uint64_t t = x & m[1 + i];
+        x = (x ^ t) | (t >> (1u << i));
+    }
+    return x;
+}
+
 // Tiles [t0, t1) of one tensor's line, processed by one workgroup.  The LDS
 // table is initialized here and fully flushed by the last tile.
-template <int LPN, typename FT, int WORDS, int MAXO>
-__device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep, uint64_t t0, uint64_t t1) {
+// TMC: the conflict-resolution mode fixed at compile time (-1: read from the
+// arguments).  FAST: exactly 3 modes, a one-word index, gathers through
+// 32-bit buffer offsets and FP32 atomics into the output, with the
+// extraction masks in LDS (`lmask`) -- the common case, compiled without the
+// branches and the scalar state of the general one.
+template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST>
+__device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep, const uint64_t *lmask,
+                                      uint64_t t0, uint64_t t1) {
+    const int TM = TMC >= 0 ? TMC : a.tile_merge;
     // nonzeros gathered together per group
     constexpr int SB = MAXO == 2 ? (LPN < 4 ? LPN : 4) : (LPN < 2 ? LPN : 2);
     // table rows: hashed slots (tile merge) or every row of the mode (direct).
-    // Rows are rank + 1 floats apart: the odd stride spreads the rows the
+    // Rows are rank + 1 doubles apart: the odd stride spreads the rows the
     // groups of a wave update at once over all LDS banks.
-    const int S = a.tile_merge == 1 ? (1 << a.slots_log2) : (a.tile_merge == 2 ? (int)a.dim_out : 0);
-    const int SK = a.tile_merge == 1 ? S : 0;  // key / hit arrays
+    const int S = TM == 1 ? (1 << a.slots_log2) : (TM == 2 ? (int)a.dim_out : 0);
+    const int SK = TM == 1 ? S : 0;  // key / hit arrays
     const int TS = a.rank + 1;
     uint32_t *tkey = smem;
     uint32_t *thits = smem + SK;
-    float *tval = (float *)(smem + 2 * SK);
-    uint32_t *stage = smem + ((2 * SK + (size_t)S * TS + 3) & ~(size_t)3);
+    double *tval = (double *)(smem + 2 * SK);  // 2 * SK is even: 8-byte aligned
+    uint32_t *stage = smem + ((2 * SK + 2 * (size_t)S * TS + 3) & ~(size_t)3);
     const int REC = a.rec;  // [val, destination, other coordinates...], multiple of 4
     const int tid = threadIdx.x;
     const int q = tid & (LPN - 1);
@@ -193,14 +222,14 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
     uint32_t *gst = stage + grp * LPN * REC;
     const int r0 = 4 * q;
     const bool ract = r0 < a.rank;
-    const int nother = a.nmodes - 1;
+    const int nother = FAST ? 2 : a.nmodes - 1;
 
-    if (a.tile_merge) {
+    if (TM) {
         for (int i = tid; i < SK; i += blockDim.x) {
             tkey[i] = kEmptyRow;
             thits[i] = 0;
         }
-        for (int i = tid; i < S * TS; i += blockDim.x) tval[i] = 0.f;
+        for (int i = tid; i < S * TS; i += blockDim.x) tval[i] = 0.0;
         __syncthreads();
     }
 
@@ -237,7 +266,11 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             if (x < gb) {
                 uint32_t c3[3] = {0u, 0u, 0u};
                 uint32_t row;
-                if (MAXO == 2 && WORDS == 1) {
+                if (FAST) {
+#pragma unroll
+                    for (int m = 0; m < 3; m++) c3[m] = (uint32_t)compress_lds(lo, lmask + 7 * m);
+                    row = a.mode == 0 ? c3[0] : (a.mode == 1 ? c3[1] : c3[2]);
+                } else if (MAXO == 2 && WORDS == 1) {
 #pragma unroll
                     for (int m = 0; m < 3; m++)
                         if (m < a.nmodes) c3[m] = extract_mode<1>(a.lp.mode[m], lo, hi);
@@ -251,10 +284,10 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
                 uint32_t dst = kEmptyRow;
                 if (row_ok) {
                     dst = row;
-                    if (a.tile_merge == 1) {
+                    if (TM == 1) {
                         const uint32_t slot = table_slot(tkey, row, a.slots_log2);
                         if (slot != kNoSlot) dst = kSlotBit | slot;
-                    } else if (a.tile_merge == 2) {
+                    } else if (TM == 2) {
                         dst = kSlotBit | row;
                     }
                 }
@@ -311,7 +344,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
 #pragma unroll
                     for (int k = 0; k < MAXO; k++) {
                         if (k < nother) {
-                            if (a.buf32) {
+                            if (FAST || a.buf32) {
                                 const __amdgpu_buffer_rsrc_t rs = factor_rsrc(a.fac_other[k], a.fac_bytes[k]);
 #pragma unroll
                                 for (int s = 0; s < SB; s++) {
@@ -364,7 +397,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
 #pragma unroll
                             for (int j = 0; j < 4; j++) acc[j] += p[s][j];
                         } else {
-                            if (cur != kEmptyRow) flush_run(a, tval, thits, cur, q, r0, acc);
+                            if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
                             cur = dst;
 #pragma unroll
                             for (int j = 0; j < 4; j++) acc[j] = p[s][j];
@@ -374,21 +407,21 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             }
             __builtin_amdgcn_wave_barrier();
         }
-        if (cur != kEmptyRow) flush_run(a, tval, thits, cur, q, r0, acc);
+        if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
 
-        if (a.tile_merge == 2 && t + 1 == t1) {
+        if (TM == 2 && t + 1 == t1) {
             // ---- end of the stretch: every row of the mode held in LDS is
             // added to the output once
             __syncthreads();
             const int qr = a.rank >> 2;
             for (int i = tid; i < S * qr; i += blockDim.x) {
                 const int row = i / qr, part = i - row * qr;
-                const float *tv = tval + (size_t)row * TS + part * 4;
-                const float vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                if (vv[0] != 0.f || vv[1] != 0.f || vv[2] != 0.f || vv[3] != 0.f) global_add(a, (uint32_t)row, part * 4, vv);
+                const double *tv = tval + (size_t)row * TS + part * 4;
+                const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
+                if (vv[0] != 0.0 || vv[1] != 0.0 || vv[2] != 0.0 || vv[3] != 0.0) global_add<FAST>(a, (uint32_t)row, part * 4, vv);
             }
             __syncthreads();
-        } else if (a.tile_merge == 1) {
+        } else if (TM == 1) {
             // ---- tile end: rows merged many times in this tile (high reuse)
             // stay in LDS for the next tile; the others are added to the
             // output and their slots cleared.  Everything is flushed every
@@ -408,13 +441,13 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             for (int i = tid; i < S * qr; i += blockDim.x) {
                 const int slot = i / qr, part = i - slot * qr;
                 if (thits[slot] == kFlushMark) {
-                    float *tv = tval + (size_t)slot * TS + part * 4;
-                    const float vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                    global_add(a, tkey[slot], part * 4, vv);
-                    tv[0] = 0.f;
-                    tv[1] = 0.f;
-                    tv[2] = 0.f;
-                    tv[3] = 0.f;
+                    double *tv = tval + (size_t)slot * TS + part * 4;
+                    const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
+                    global_add<FAST>(a, tkey[slot], part * 4, vv);
+                    tv[0] = 0.0;
+                    tv[1] = 0.0;
+                    tv[2] = 0.0;
+                    tv[3] = 0.0;
                 }
             }
             __syncthreads();
@@ -441,13 +474,23 @@ __device__ inline void stretch_of(uint64_t total, int xcd_map, uint64_t *g0, uin
 
 // Kernel variants: MAXO = most other modes handled with fully unrolled
 // gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
-template <int LPN, typename FT, int WORDS, int MAXO>
+template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST>
 __global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ uint32_t nkeep;
+    __shared__ uint64_t lmask[FAST ? 21 : 1];
+    if (FAST) {
+        // the 3 modes' extraction masks: the AND mask, then the 6 move masks
+        const int i = threadIdx.x;
+        if (i < 21) {
+            const WordMasks &w = a.lp.mode[i / 7].w[0];
+            lmask[i] = i % 7 == 0 ? w.mask : w.mv[i % 7 - 1];
+        }
+        __syncthreads();
+    }
     uint64_t t0, t1;
     stretch_of(a.ntiles, a.xcd_map, &t0, &t1);
-    mttkrp_stretch<LPN, FT, WORDS, MAXO>(a, smem, nkeep, t0, t1);
+    mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
 }
 
 // Many tensors in one persistent launch: the tiles of all jobs form one
@@ -471,7 +514,7 @@ __global__ __launch_bounds__(256) void k_mttkrp_batch(const MttkrpArgs *__restri
         const uint64_t a0 = prefix[j], a1 = prefix[j + 1];
         const uint64_t t0 = (g0 > a0 ? g0 : a0) - a0, t1 = (g1 < a1 ? g1 : a1) - a0;
         if (t0 < t1) {
-            mttkrp_stretch<LPN, FT, WORDS, MAXO>(jobs[j], smem, nkeep, t0, t1);
+            mttkrp_stretch<LPN, FT, WORDS, MAXO, -1, false>(jobs[j], smem, nkeep, nullptr, t0, t1);
             __syncthreads();
         }
     }
@@ -503,10 +546,31 @@ __global__ void k_sum_copies(const T *__restrict__ in, int copies, uint64_t n, f
 template <int LPN, typename FT, int WORDS>
 const void *kernel_ptr(int nmodes, bool batch) {
     if (nmodes <= 3)
-        return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 2> : (const void *)k_mttkrp<LPN, FT, WORDS, 2>;
+        return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 2>
+                     : (const void *)k_mttkrp<LPN, FT, WORDS, 2, -1, false>;
     if (nmodes <= 5)
-        return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 4> : (const void *)k_mttkrp<LPN, FT, WORDS, 4>;
-    return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 7> : (const void *)k_mttkrp<LPN, FT, WORDS, 7>;
+        return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 4>
+                     : (const void *)k_mttkrp<LPN, FT, WORDS, 4, -1, false>;
+    return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 7> : (const void *)k_mttkrp<LPN, FT, WORDS, 7, -1, false>;
+}
+
+template <int LPN, typename FT>
+const void *fast_ptr(int tile_merge) {
+    return tile_merge == 1   ? (const void *)k_mttkrp<LPN, FT, 1, 2, 1, true>
+           : tile_merge == 2 ? (const void *)k_mttkrp<LPN, FT, 1, 2, 2, true>
+                             : (const void *)k_mttkrp<LPN, FT, 1, 2, 0, true>;
+}
+
+template <typename FT>
+const void *pick_fast(int lpn, int tile_merge) {
+    switch (lpn) {
+        case 1: return fast_ptr<1, FT>(tile_merge);
+        case 2: return fast_ptr<2, FT>(tile_merge);
+        case 4: return fast_ptr<4, FT>(tile_merge);
+        case 8: return fast_ptr<8, FT>(tile_merge);
+        case 16: return fast_ptr<16, FT>(tile_merge);
+        default: return fast_ptr<32, FT>(tile_merge);
+    }
 }
 
 template <typename FT, int WORDS>
@@ -529,12 +593,22 @@ const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch) {
     return words == 2 ? pick_lpn<float, 2>(lpn, nmodes, batch) : pick_lpn<float, 1>(lpn, nmodes, batch);
 }
 
+// The specialised kernel serves 3-mode tensors with a one-word index whose
+// factor reads fit 32-bit offsets and whose updates go straight to the FP32
+// output; everything else takes the general kernel.
+const void *pick_single(int lpn, int fdt, int words, const MttkrpArgs &a) {
+    if (words == 1 && a.nmodes == 3 && a.buf32 && !a.use64 && a.copies == 1)
+        return fdt == ALTO_BF16 ? pick_fast<uint16_t>(lpn, a.tile_merge) : pick_fast<float>(lpn, a.tile_merge);
+    return pick_kernel(lpn, fdt, words, a.nmodes, false);
+}
+
 const void *zero_outputs_kernel() { return (const void *)k_zero_outputs; }
 
 namespace {
 
 struct DevProps {
     int cus = 0;
+    size_t lds = 0;  // LDS bytes one workgroup may allocate
 };
 
 DevProps &props(int dev);
@@ -542,14 +616,26 @@ DevProps &props(int dev);
 
 int device_cus(int dev) { return props(dev).cus; }
 
+size_t direct_table_limit(const alto_tensor *h, int threads) {
+    const size_t rec = (size_t)((2 + h->info.nmodes - 1 + 3) & ~3);  // record words per nonzero
+    const size_t stage = (size_t)threads * rec * 4 + 256;              // + static LDS and alignment
+    const size_t lds = props(h->device).lds;
+    return lds > stage ? lds - stage : 0;
+}
+
 namespace {
 
 DevProps &props(int dev) {
     static DevProps p[64];
     if (dev >= 0 && dev < 64 && p[dev].cus == 0) {
         hipDeviceProp_t dp;
-        if (hipGetDeviceProperties(&dp, dev) == hipSuccess) p[dev].cus = dp.multiProcessorCount;
-        else p[dev].cus = 256;
+        if (hipGetDeviceProperties(&dp, dev) == hipSuccess) {
+            p[dev].cus = dp.multiProcessorCount;
+            p[dev].lds = dp.sharedMemPerBlock;
+        } else {
+            p[dev].cus = 256;
+            p[dev].lds = 64 * 1024;
+        }
     }
     return p[dev < 0 || dev >= 64 ? 0 : dev];
 }
@@ -577,7 +663,7 @@ alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt)
     // operations a buffered update costs in the worst case
     p.conflict = reuse > 4.0 ? ALTO_CR_TILE : ALTO_CR_RUN;
     p.block_threads = 256;
-    // LDS table of about 32 KiB of FP32 partial rows
+    // LDS table of about 64 KiB of FP64 partial rows
     int slots = 8192 / rank;
     int s2 = 1;
     while (s2 * 2 <= slots) s2 *= 2;
@@ -591,13 +677,13 @@ alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt)
     // 8 columns) is accumulated there for the workgroup's whole segment
     for (int rt = rank; rt >= 8 && rt % 4 == 0; rt /= 2) {
         if (rank % rt) break;
-        const size_t bytes = (size_t)h->info.dims[mode] * (rt + 1) * 4;
-        if (bytes <= kDirectLdsBytes && reuse > 4.0) {
+        const size_t bytes = (size_t)h->info.dims[mode] * (rt + 1) * 8;
+        if (bytes <= direct_table_limit(h, 512) && reuse > 4.0) {
             p.conflict = ALTO_CR_DIRECT;
             p.rank_tile = rt == rank ? 0 : rt;
             // one workgroup per CU when the table takes most of the LDS:
             // give it more waves
-            if (bytes > kDirectLdsBytes / 2) p.block_threads = 512;
+            if (bytes > direct_table_limit(h, 256) / 2) p.block_threads = 512;
             break;
         }
     }
@@ -653,15 +739,16 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
     if (p.rank_tile < 0 || p.rank_tile % 4 || (p.rank_tile > 0 && rank % p.rank_tile))
         return fail(ALTO_ERR_ARG, "rank_tile must be a multiple of 4 dividing rank");
     const int rt = p.rank_tile > 0 ? p.rank_tile : rank;
-    if (p.conflict == ALTO_CR_DIRECT && (size_t)h->info.dims[mode] * (rt + 1) * 4 > kDirectLdsBytes)
-        return fail(ALTO_ERR_ARG, "mode too long to hold in LDS for this rank tile");
     if (p.block_threads != 256 && p.block_threads != 512) return fail(ALTO_ERR_ARG, "block_threads must be 256 or 512");
+    if (p.conflict == ALTO_CR_DIRECT &&
+        (size_t)h->info.dims[mode] * (rt + 1) * 8 > direct_table_limit(h, p.block_threads))
+        return fail(ALTO_ERR_ARG, "mode too long to hold in LDS for this rank tile");
     if (p.tile_nnz < 1) return fail(ALTO_ERR_ARG, "tile_nnz must be positive");
     if (p.conflict == ALTO_CR_TILE) {
         if (p.table_slots < 16 || (p.table_slots & (p.table_slots - 1)))
             return fail(ALTO_ERR_ARG, "table_slots must be a power of two >= 16");
-        const size_t lds = (size_t)p.table_slots * (rt + 2) * 4;
-        if (lds > 96 * 1024) return fail(ALTO_ERR_ARG, "LDS table too large for rank");
+        const size_t lds = (size_t)p.table_slots * (2 * (rt + 1) + 2) * 4;  // FP64 row + key + hits
+        if (lds > 144 * 1024) return fail(ALTO_ERR_ARG, "LDS table too large for rank");
     }
     *out = p;
     return ALTO_OK;
@@ -747,7 +834,7 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
 size_t lds_bytes(const MttkrpArgs &a, int threads) {
     const size_t S = a.tile_merge == 1 ? ((size_t)1 << a.slots_log2) : (a.tile_merge == 2 ? a.dim_out : 0);
     const size_t SK = a.tile_merge == 1 ? S : 0;
-    return ((2 * SK + S * (a.rank + 1) + 3) & ~(size_t)3) * 4 + (size_t)threads * a.rec * 4;
+    return ((2 * SK + 2 * S * (a.rank + 1) + 3) & ~(size_t)3) * 4 + (size_t)threads * a.rec * 4;
 }
 
 // ---- optional per-launch timing with HIP events
@@ -805,7 +892,7 @@ void timing_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
 
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s) {
     const int lpn = lpn_for(a.rank);
-    const void *kern = pick_kernel(lpn, fdt, h->info.index_words, a.nmodes, false);
+    const void *kern = pick_single(lpn, fdt, h->info.index_words, a);
     const size_t lds = lds_bytes(a, threads);
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) {
