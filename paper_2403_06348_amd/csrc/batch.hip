@@ -236,7 +236,7 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
     for (int rt = rank; rt >= 4; rt /= 2) {
         if (rt % 4 || rank % rt) break;
         for (int threads : {256, 512}) {
-            if ((size_t)h->info.dims[mode] * (rt + 1) * 8 > direct_table_limit(h, threads)) continue;
+            if ((size_t)h->info.dims[mode] * (rt + 1) * 4 > direct_table_limit(h, threads)) continue;
             alto_mttkrp_plan p = base;
             p.conflict = ALTO_CR_DIRECT;
             p.rank_tile = rt == rank ? 0 : rt;

@@ -27,6 +27,7 @@ struct MttkrpArgs {
     uint64_t tq, tr;  // nnz / ntiles, nnz % ntiles
     int mode, rank, nmodes;
     int tile_merge;   // 0: direct atomics, 1: LDS table merge, 2: whole mode in LDS
+    int tw;           // 32-bit words per LDS table element: 2 = FP64, 1 = FP32
     int use64;        // 1: accumulate into out64
     int slots_log2;
     int rec;          // staged record length (u32) per nonzero

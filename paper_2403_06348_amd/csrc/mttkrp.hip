@@ -150,20 +150,53 @@ __device__ inline uint32_t table_slot(uint32_t *tkey, uint32_t row, int log2s) {
 // an LDS slot, else the output row itself (rows are below 2^31).
 constexpr uint32_t kSlotBit = 0x80000000u;
 
+// FP32 add to 4 LDS words by compare-and-swap, the 4 swaps of a round in
+// flight together.  gfx950's LDS runs ds_add_f32 about 12x slower than a
+// swap loop (193 against 16 CU-cycles per wave instruction, measured with
+// distinct addresses); a lost race retries with the value the swap returned.
+__device__ inline void lds_add4_f32(float *t, const float *v, int n) {
+    uint32_t *u = (uint32_t *)t;
+    uint32_t old[4];
+    bool todo[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        todo[j] = j < n;
+        old[j] = todo[j] ? u[j] : 0u;
+    }
+    while (todo[0] || todo[1] || todo[2] || todo[3]) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (todo[j]) {
+                const uint32_t want = __float_as_uint(__uint_as_float(old[j]) + v[j]);
+                const uint32_t got = atomicCAS(u + j, old[j], want);
+                todo[j] = got != old[j];
+                old[j] = got;
+            }
+        }
+    }
+}
+
 // Add a finished run of updates to its destination.  LDS rows are FP64:
-// besides the precision, gfx950's LDS adds FP64 atomically about twenty
-// times faster than FP32 (ds_add_f64 against ds_add_f32).
+// gfx950's LDS adds FP64 atomically about twenty times faster than FP32
+// (ds_add_f64 against ds_add_f32), and the partial sums gain precision.  A
+// whole-mode table whose FP64 rows would not fit (a.tw == 1) holds FP32 rows,
+// twice the columns per pass, added by compare-and-swap.
 template <int TM, bool FAST>
-__device__ inline void flush_run(const MttkrpArgs &a, double *tval, uint32_t *thits, uint32_t dst, int q, int r0,
+__device__ inline void flush_run(const MttkrpArgs &a, void *tval, uint32_t *thits, uint32_t dst, int q, int r0,
                                  const float *acc) {
     if (dst & kSlotBit) {
         const uint32_t slot = dst & ~kSlotBit;
-        double *t = tval + (uint64_t)slot * (a.rank + 1) + r0;
+        const int tm = TM >= 0 ? TM : a.tile_merge;
+        if (tm == 2 && a.tw == 1) {
+            lds_add4_f32((float *)tval + (uint64_t)slot * (a.rank + 1) + r0, acc, a.rank - r0);
+            return;
+        }
+        double *t = (double *)tval + (uint64_t)slot * (a.rank + 1) + r0;
 #pragma unroll
         for (int j = 0; j < 4; j++)
             if (r0 + j < a.rank)
                 __hip_atomic_fetch_add(t + j, (double)acc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (q == 0 && (TM >= 0 ? TM : a.tile_merge) == 1)
+        if (q == 0 && tm == 1)
             __hip_atomic_fetch_add(thits + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
         global_add<FAST>(a, dst, r0, acc);
@@ -212,8 +245,11 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
     const int TS = a.rank + 1;
     uint32_t *tkey = smem;
     uint32_t *thits = smem + SK;
-    double *tval = (double *)(smem + 2 * SK);  // 2 * SK is even: 8-byte aligned
-    uint32_t *stage = smem + ((2 * SK + 2 * (size_t)S * TS + 3) & ~(size_t)3);
+    const int TW = TM == 2 ? a.tw : 2;             // words per table element
+    void *tval = (void *)(smem + 2 * SK);          // 2 * SK is even: 8-byte aligned
+    double *tv64 = (double *)tval;
+    float *tv32 = (float *)tval;
+    uint32_t *stage = smem + ((2 * SK + (size_t)TW * S * TS + 3) & ~(size_t)3);
     const int REC = a.rec;  // [val, destination, other coordinates...], multiple of 4
     const int tid = threadIdx.x;
     const int q = tid & (LPN - 1);
@@ -229,7 +265,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             tkey[i] = kEmptyRow;
             thits[i] = 0;
         }
-        for (int i = tid; i < S * TS; i += blockDim.x) tval[i] = 0.0;
+        for (int i = tid; i < TW * S * TS; i += blockDim.x) smem[2 * SK + i] = 0u;
         __syncthreads();
     }
 
@@ -416,9 +452,17 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             const int qr = a.rank >> 2;
             for (int i = tid; i < S * qr; i += blockDim.x) {
                 const int row = i / qr, part = i - row * qr;
-                const double *tv = tval + (size_t)row * TS + part * 4;
-                const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                if (vv[0] != 0.0 || vv[1] != 0.0 || vv[2] != 0.0 || vv[3] != 0.0) global_add<FAST>(a, (uint32_t)row, part * 4, vv);
+                if (TW == 2) {
+                    const double *tv = tv64 + (size_t)row * TS + part * 4;
+                    const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
+                    if (vv[0] != 0.0 || vv[1] != 0.0 || vv[2] != 0.0 || vv[3] != 0.0)
+                        global_add<FAST>(a, (uint32_t)row, part * 4, vv);
+                } else {
+                    const float *tv = tv32 + (size_t)row * TS + part * 4;
+                    const float vv[4] = {tv[0], tv[1], tv[2], tv[3]};
+                    if (vv[0] != 0.f || vv[1] != 0.f || vv[2] != 0.f || vv[3] != 0.f)
+                        global_add<FAST>(a, (uint32_t)row, part * 4, vv);
+                }
             }
             __syncthreads();
         } else if (TM == 1) {
@@ -441,7 +485,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             for (int i = tid; i < S * qr; i += blockDim.x) {
                 const int slot = i / qr, part = i - slot * qr;
                 if (thits[slot] == kFlushMark) {
-                    double *tv = tval + (size_t)slot * TS + part * 4;
+                    double *tv = tv64 + (size_t)slot * TS + part * 4;
                     const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
                     global_add<FAST>(a, tkey[slot], part * 4, vv);
                     tv[0] = 0.0;
@@ -674,18 +718,31 @@ alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt)
     p.tile_nnz = (int)tile;
     p.accumulate = ALTO_ACC_F32;
     // a mode short enough to hold whole in LDS (with a rank tile of at least
-    // 8 columns) is accumulated there for the workgroup's whole segment
-    for (int rt = rank; rt >= 8 && rt % 4 == 0; rt /= 2) {
-        if (rank % rt) break;
-        const size_t bytes = (size_t)h->info.dims[mode] * (rt + 1) * 8;
-        if (bytes <= direct_table_limit(h, 512) && reuse > 4.0) {
-            p.conflict = ALTO_CR_DIRECT;
-            p.rank_tile = rt == rank ? 0 : rt;
-            // one workgroup per CU when the table takes most of the LDS:
-            // give it more waves
-            if (bytes > direct_table_limit(h, 256) / 2) p.block_threads = 512;
-            break;
+    // 8 columns) is accumulated there for the workgroup's whole segment: in
+    // FP64 rows if at most two passes (rank tiles) do, else in FP32 rows
+    // (twice the columns per pass, slower adds)
+    const size_t lim = direct_table_limit(h, 512);
+    int rt_d = 0;
+    size_t bytes_d = 0;
+    for (int eb : {8, 4}) {
+        for (int rt = rank; rt >= 8 && rt % 4 == 0 && rank % rt == 0; rt /= 2) {
+            const size_t bytes = (size_t)h->info.dims[mode] * (rt + 1) * eb;
+            if (bytes <= lim) {
+                if (eb == 4 || 2 * rt >= rank) {
+                    rt_d = rt;
+                    bytes_d = bytes;
+                }
+                break;
+            }
         }
+        if (rt_d) break;
+    }
+    if (rt_d && reuse > 4.0) {
+        p.conflict = ALTO_CR_DIRECT;
+        p.rank_tile = rt_d == rank ? 0 : rt_d;
+        // one workgroup per CU when the table takes most of the LDS: give it
+        // more waves
+        if (bytes_d > direct_table_limit(h, 256) / 2) p.block_threads = 512;
     }
     (void)fdt;
     return p;
@@ -741,7 +798,7 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
     const int rt = p.rank_tile > 0 ? p.rank_tile : rank;
     if (p.block_threads != 256 && p.block_threads != 512) return fail(ALTO_ERR_ARG, "block_threads must be 256 or 512");
     if (p.conflict == ALTO_CR_DIRECT &&
-        (size_t)h->info.dims[mode] * (rt + 1) * 8 > direct_table_limit(h, p.block_threads))
+        (size_t)h->info.dims[mode] * (rt + 1) * 4 > direct_table_limit(h, p.block_threads))
         return fail(ALTO_ERR_ARG, "mode too long to hold in LDS for this rank tile");
     if (p.tile_nnz < 1) return fail(ALTO_ERR_ARG, "tile_nnz must be positive");
     if (p.conflict == ALTO_CR_TILE) {
@@ -829,12 +886,18 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
     while ((1 << l2) < p.table_slots) l2++;
     a->slots_log2 = l2;
     a->rec = ((h->info.nmodes + 1) + 3) / 4 * 4;
+    // whole-mode rows are FP64 when this rank tile fits so, else FP32
+    a->tw = 2;
+    if (a->tile_merge == 2 &&
+        (size_t)h->info.dims[mode] * (a->rank + 1) * 8 > direct_table_limit(h, p.block_threads))
+        a->tw = 1;
 }
 
 size_t lds_bytes(const MttkrpArgs &a, int threads) {
     const size_t S = a.tile_merge == 1 ? ((size_t)1 << a.slots_log2) : (a.tile_merge == 2 ? a.dim_out : 0);
     const size_t SK = a.tile_merge == 1 ? S : 0;
-    return ((2 * SK + 2 * S * (a.rank + 1) + 3) & ~(size_t)3) * 4 + (size_t)threads * a.rec * 4;
+    const size_t TW = a.tile_merge == 2 ? (size_t)a.tw : 2;  // words per table element
+    return ((2 * SK + TW * S * (a.rank + 1) + 3) & ~(size_t)3) * 4 + (size_t)threads * a.rec * 4;
 }
 
 // ---- optional per-launch timing with HIP events

@@ -160,9 +160,11 @@ def test_mttkrp_graph_capture_replays_match_eager():
 
 
 @pytest.mark.parametrize("name,rank,mode,plan", [
-    # 2048 rows x 9 FP64 columns: 147 KiB, fits beside the staging of 256 threads
     ("c3s", 32, 1, dict(conflict=alto.CR_DIRECT, rank_tile=8, block_threads=256)),
-    ("c3s", 32, 1, dict(conflict=alto.CR_DIRECT, rank_tile=4, block_threads=512)),
+    # 2048 rows x 17 FP32 columns: 136 KiB of the 160 KiB LDS
+    ("c3s", 32, 1, dict(conflict=alto.CR_DIRECT, rank_tile=16, block_threads=512)),
+    # 1024 rows, all 32 columns in one pass
+    ("c3s", 32, 2, dict(conflict=alto.CR_DIRECT, rank_tile=32, block_threads=512)),
     ("c3s", 32, 2, dict(conflict=alto.CR_DIRECT, rank_tile=16)),
     ("c3s", 32, 2, dict(conflict=alto.CR_DIRECT, rank_tile=16, block_threads=512)),
     ("unit", 20, 0, dict(conflict=alto.CR_DIRECT)),
@@ -191,9 +193,9 @@ def test_whole_mode_lds_rejects_long_modes():
         T.mttkrp(0, gf, plan=dict(conflict=alto.CR_DIRECT))
     with pytest.raises(alto.AltoError):
         T.mttkrp(0, gf, plan=dict(rank_tile=12))
-    # whole mode fits with 256 threads' staging, not with 512 threads'
+    # 2048 rows x 33 FP32 columns (264 KiB) exceed the LDS; 17 columns fit
     X3, T3 = built("c3s")
     g3 = [torch.rand(d, 32, device="cuda") for d in X3.dims]
-    T3.mttkrp(1, g3, plan=dict(conflict=alto.CR_DIRECT, rank_tile=8, block_threads=256))
+    T3.mttkrp(1, g3, plan=dict(conflict=alto.CR_DIRECT, rank_tile=16, block_threads=512))
     with pytest.raises(alto.AltoError):
-        T3.mttkrp(1, g3, plan=dict(conflict=alto.CR_DIRECT, rank_tile=8, block_threads=512))
+        T3.mttkrp(1, g3, plan=dict(conflict=alto.CR_DIRECT, rank_tile=32))
