@@ -33,6 +33,7 @@ constexpr int kThreads = 256;
 constexpr int kChunk = 32;        // rows staged per step
 constexpr int kPartials = 512;    // partial Gram blocks
 constexpr int kMaxSweepRank = 64;
+constexpr uint64_t kBatchAloneNnz = uint64_t(1) << 21;  // a job this large fills the GPU alone
 
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
     const uint32_t u = __float_as_uint(f);
@@ -81,14 +82,30 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const float *__restri
         if (re[j] >= 0) o[re[j] * R + se[j]] = acc[j];
 }
 
+// G = sum of the np partial R x R blocks.  Block b owns entries
+// [64 b, 64 b + 64); its 4 waves take every 4th partial with two independent
+// sums each, then add their results in a fixed order (deterministic).
 __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double *__restrict__ partials, int np, int R,
                                                           double *__restrict__ G) {
-    for (int e = threadIdx.x; e < R * R; e += kThreads) {
-        double s = 0.0;
-        for (int p = 0; p < np; p++) s += partials[(uint64_t)p * R * R + e];
-        G[e] = s;
+    __shared__ double red[4][64];
+    const int rr = R * R;
+    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + t;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < rr) {
+        int p = w;
+        for (; p + 4 < np; p += 8) {
+            s0 += partials[(uint64_t)p * rr + e];
+            s1 += partials[(uint64_t)(p + 4) * rr + e];
+        }
+        for (; p < np; p += 4) s0 += partials[(uint64_t)p * rr + e];
     }
+    red[w][t] = s0 + s1;
+    __syncthreads();
+    if (w == 0 && e < rr) G[e] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
+
+inline unsigned gram_reduce_blocks(int R) { return (unsigned)((R * R + 63) / 64); }
 
 // Single workgroup.  grams: N x R x R; W: R x R output; flags bit n on fallback.
 __global__ __launch_bounds__(kThreads) void k_als_prepare(const double *__restrict__ grams, int N, int n, int R,
@@ -278,19 +295,13 @@ __global__ __launch_bounds__(kThreads) void k_als_apply(const float *__restrict_
         if (re[j] >= 0) o[re[j] * R + se[j]] = acc[j];
 }
 
-__global__ __launch_bounds__(kThreads) void k_als_finalize(const double *__restrict__ partials, int np, int R,
-                                                           double *__restrict__ Gn, double *__restrict__ lam_ws,
+// Gn holds the Gram of the updated (unnormalized) factor: lambda = the
+// column norms, then Gn is rescaled in place to the normalized factor's Gram.
+__global__ __launch_bounds__(kThreads) void k_als_finalize(double *__restrict__ Gn, int R, double *__restrict__ lam_ws,
                                                            double *__restrict__ lam_out) {
     __shared__ double lam[kMaxSweepRank];
-    __shared__ double G[kMaxSweepRank * kMaxSweepRank];
-    for (int e = threadIdx.x; e < R * R; e += kThreads) {
-        double s = 0.0;
-        for (int p = 0; p < np; p++) s += partials[(uint64_t)p * R * R + e];
-        G[e] = s;
-    }
-    __syncthreads();
     for (int r = threadIdx.x; r < R; r += kThreads) {
-        const double l = sqrt(fmax(G[r * R + r], 0.0));
+        const double l = sqrt(fmax(Gn[r * R + r], 0.0));
         lam[r] = l;
         lam_ws[r] = l;
         if (lam_out) lam_out[r] = l;
@@ -299,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void k_als_finalize(const double *__restr
     for (int e = threadIdx.x; e < R * R; e += kThreads) {
         const int r = e / R, s = e % R;
         const double d = lam[r] * lam[s];
-        Gn[e] = d > 0.0 ? G[e] / d : 0.0;
+        Gn[e] = d > 0.0 ? Gn[e] / d : 0.0;
     }
 }
 
@@ -383,7 +394,8 @@ alto_status sweep_begin(alto_tensor *h, int rank, int fdt, float *const *factors
         const uint64_t I = h->info.dims[m];
         const unsigned P = partial_blocks(I);
         ALTO_ENT_DISPATCH(ent, k_gram_partial, dim3(P), dim3(kThreads), 0, s, factors[m], I, R, partials);
-        hipLaunchKernelGGL(k_gram_reduce, dim3(1), dim3(kThreads), 0, s, partials, (int)P, R, grams + m * rr);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(R)), dim3(kThreads), 0, s, partials, (int)P, R,
+                           grams + m * rr);
         if (fdt == ALTO_BF16)
             hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(I * R, 256, 16384)), dim3(256), 0, s, factors[m], I * R,
                                h->ws_bf16[m]);
@@ -419,8 +431,9 @@ alto_status sweep_post(alto_tensor *h, int n, int rank, int fdt, float *const *f
     const unsigned P = partial_blocks(I);
     const int ent = ent_for(R);
     ALTO_ENT_DISPATCH(ent, k_als_apply, dim3(P), dim3(kThreads), 0, s, h->ws_m, W, factors[n], I, R, partials);
-    hipLaunchKernelGGL(k_als_finalize, dim3(1), dim3(kThreads), 0, s, partials, (int)P, R, grams + n * rr, lam_ws,
-                       lambda);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(R)), dim3(kThreads), 0, s, partials, (int)P, R,
+                       grams + n * rr);
+    hipLaunchKernelGGL(k_als_finalize, dim3(1), dim3(kThreads), 0, s, grams + n * rr, R, lam_ws, lambda);
     hipLaunchKernelGGL(k_als_normalize, dim3(grid_for(I * R, 256, 16384)), dim3(256), 0, s, factors[n], I, R, lam_ws,
                        fdt == ALTO_BF16 ? h->ws_bf16[n] : nullptr);
     ALTO_HIP(hipGetLastError());
@@ -469,6 +482,10 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *r
     }
     std::vector<const void *> fptr((size_t)count * ALTO_MAX_MODES);
     for (int j = 0; j < count; j++) sweep_factor_ptrs(hs[j], fdts[j], factors[j], &fptr[(size_t)j * ALTO_MAX_MODES]);
+    // a job that fills the GPU by itself runs its own launch with its mode's
+    // plan (whole-mode LDS, rank tiles); the small ones share persistent
+    // launches
+    auto alone = [&](int j) { return hs[j]->info.nnz >= kBatchAloneNnz; };
     std::vector<alto_handle> bh;
     std::vector<int> bm, br, bf;
     std::vector<const void *const *> bfac;
@@ -479,6 +496,14 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *r
             if (n >= hs[j]->info.nmodes) continue;
             alto_status st = sweep_pre(hs[j], n, ranks[j], s);
             if (st != ALTO_OK) return st;
+            if (alone(j)) {
+                alto_mttkrp_plan p;
+                st = resolve_plan(hs[j], n, ranks[j], fdts[j], nullptr, &p);
+                if (st != ALTO_OK) return st;
+                st = run_mttkrp(hs[j], n, ranks[j], fdts[j], &fptr[(size_t)j * ALTO_MAX_MODES], hs[j]->ws_m, p, s);
+                if (st != ALTO_OK) return st;
+                continue;
+            }
             bh.push_back(hs[j]);
             bm.push_back(n);
             br.push_back(ranks[j]);
@@ -488,8 +513,9 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *r
         }
         // the MTTKRPs of mode n of every job in one persistent launch per
         // kernel variant
-        alto_status st = batched_run((int)bh.size(), bh.data(), bm.data(), br.data(), bf.data(), bfac.data(),
-                                     bout.data(), s);
+        alto_status st = bh.empty() ? ALTO_OK
+                                    : batched_run((int)bh.size(), bh.data(), bm.data(), br.data(), bf.data(),
+                                                  bfac.data(), bout.data(), s);
         if (st != ALTO_OK) return st;
         for (int j = 0; j < count; j++) {
             if (n >= hs[j]->info.nmodes) continue;
