@@ -95,6 +95,8 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
     }
     if (prefix[nj] == 0) return ALTO_OK;
     const void *kern = pick_kernel(g.lpn, g.fdt, g.words, jobs[0].nmodes, true);
+    alto_status lst = check_launch_lds(kern, lds, dev);
+    if (lst != ALTO_OK) return lst;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1) {
         (void)hipGetLastError();
@@ -215,7 +217,7 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
                 p.block_threads = threads;
                 p.tile_nnz = tile;
                 p.table_slots = std::max(64, base.table_slots * f / 2);
-                if ((size_t)p.table_slots * (2 * rank + 4) * 4 > 144 * 1024) continue;
+                if (!tile_plan_fits(h, rank, p.table_slots, threads)) continue;
                 cands.push_back(p);
             }
         }
@@ -229,6 +231,7 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
             p.tile_nnz = tile;
             p.rank_tile = rt;
             p.table_slots = std::max(64, pow2_floor(8192 / rt));
+            if (!tile_plan_fits(h, rt, p.table_slots, p.block_threads)) continue;
             cands.push_back(p);
         }
     }

@@ -61,6 +61,13 @@ const void *pick_single(int lpn, int fdt, int words, const MttkrpArgs &a);
 // Largest whole-mode LDS table (bytes) a workgroup of `threads` can hold
 // beside its record staging on this tensor's device.
 size_t direct_table_limit(const alto_tensor *h, int threads);
+// LDS bytes of a hashed-table plan (table, record staging, static LDS), and
+// whether it fits one workgroup on this tensor's device.
+size_t tile_plan_lds(const alto_tensor *h, int rank_tile, int slots, int threads);
+bool tile_plan_fits(const alto_tensor *h, int rank_tile, int slots, int threads);
+// ALTO_ERR_ARG when `dyn` bytes of dynamic LDS plus the kernel's static LDS
+// exceed what a workgroup may allocate on device `dev`.
+alto_status check_launch_lds(const void *kern, size_t dyn, int dev);
 const void *zero_outputs_kernel();
 int device_cus(int dev);
 

@@ -212,6 +212,73 @@ __device__ inline uint32_t rec_coord(const uint4 &h, const uint4 &h2, int k) {
 
 // Kernel variants: MAXO = most other modes handled with fully unrolled
 // gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
+// End of tile t of the stretch [t0, t1): the LDS table's rows go to the
+// output -- for a whole-mode table (TM 2) once, at the stretch's end; for a
+// hashed table (TM 1) every tile, except rows merged many times (high
+// reuse), which stay for the next tile.  Everything is flushed every
+// kKeepTiles tiles and at the end of the stretch.
+template <bool FAST>
+__device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int TS, uint32_t *tkey, uint32_t *thits,
+                                void *tval, uint32_t &nkeep, uint64_t t, uint64_t t0, uint64_t t1) {
+    const int tid = threadIdx.x;
+    double *tv64 = (double *)tval;
+    float *tv32 = (float *)tval;
+    if (TM == 2 && t + 1 == t1) {
+        // ---- end of the stretch: every row of the mode held in LDS is
+        // added to the output once
+        __syncthreads();
+        const int qr = a.rank >> 2;
+        for (int i = tid; i < S * qr; i += blockDim.x) {
+            const int row = i / qr, part = i - row * qr;
+            if (TW == 2) {
+                const double *tv = tv64 + (size_t)row * TS + part * 4;
+                const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
+                if (vv[0] != 0.0 || vv[1] != 0.0 || vv[2] != 0.0 || vv[3] != 0.0)
+                    global_add<FAST>(a, (uint32_t)row, part * 4, vv);
+            } else {
+                const float *tv = tv32 + (size_t)row * TS + part * 4;
+                const float vv[4] = {tv[0], tv[1], tv[2], tv[3]};
+                if (vv[0] != 0.f || vv[1] != 0.f || vv[2] != 0.f || vv[3] != 0.f)
+                    global_add<FAST>(a, (uint32_t)row, part * 4, vv);
+            }
+        }
+        __syncthreads();
+    } else if (TM == 1) {
+        __syncthreads();
+        const bool flush_all = (t + 1 == t1) || ((t - t0 + 1) % kKeepTiles == 0);
+        if (tid == 0) nkeep = 0;
+        __syncthreads();
+        for (int i = tid; i < S; i += blockDim.x) {
+            if (tkey[i] == kEmptyRow) continue;
+            bool keep = false;
+            if (!flush_all && thits[i] >= kHotHits) keep = atomicAdd(&nkeep, 1u) < (uint32_t)(S / 4);
+            thits[i] = keep ? 0u : kFlushMark;
+        }
+        __syncthreads();
+        const int qr = a.rank >> 2;
+        for (int i = tid; i < S * qr; i += blockDim.x) {
+            const int slot = i / qr, part = i - slot * qr;
+            if (thits[slot] == kFlushMark) {
+                double *tv = tv64 + (size_t)slot * TS + part * 4;
+                const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
+                global_add<FAST>(a, tkey[slot], part * 4, vv);
+                tv[0] = 0.0;
+                tv[1] = 0.0;
+                tv[2] = 0.0;
+                tv[3] = 0.0;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < S; i += blockDim.x) {
+            if (thits[i] == kFlushMark) {
+                tkey[i] = kEmptyRow;
+                thits[i] = 0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Compress one 64-bit index word with masks read from LDS (every lane reads
 // the same address: a broadcast).
 __device__ inline uint64_t compress_lds(uint64_t x, const uint64_t *m) {
@@ -247,8 +314,6 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
     uint32_t *thits = smem + SK;
     const int TW = TM == 2 ? a.tw : 2;             // words per table element
     void *tval = (void *)(smem + 2 * SK);          // 2 * SK is even: 8-byte aligned
-    double *tv64 = (double *)tval;
-    float *tv32 = (float *)tval;
     uint32_t *stage = smem + ((2 * SK + (size_t)TW * S * TS + 3) & ~(size_t)3);
     const int REC = a.rec;  // [val, destination, other coordinates...], multiple of 4
     const int tid = threadIdx.x;
@@ -445,64 +510,153 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
         }
         if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
 
-        if (TM == 2 && t + 1 == t1) {
-            // ---- end of the stretch: every row of the mode held in LDS is
-            // added to the output once
-            __syncthreads();
-            const int qr = a.rank >> 2;
-            for (int i = tid; i < S * qr; i += blockDim.x) {
-                const int row = i / qr, part = i - row * qr;
-                if (TW == 2) {
-                    const double *tv = tv64 + (size_t)row * TS + part * 4;
-                    const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                    if (vv[0] != 0.0 || vv[1] != 0.0 || vv[2] != 0.0 || vv[3] != 0.0)
-                        global_add<FAST>(a, (uint32_t)row, part * 4, vv);
-                } else {
-                    const float *tv = tv32 + (size_t)row * TS + part * 4;
-                    const float vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                    if (vv[0] != 0.f || vv[1] != 0.f || vv[2] != 0.f || vv[3] != 0.f)
-                        global_add<FAST>(a, (uint32_t)row, part * 4, vv);
-                }
-            }
-            __syncthreads();
-        } else if (TM == 1) {
-            // ---- tile end: rows merged many times in this tile (high reuse)
-            // stay in LDS for the next tile; the others are added to the
-            // output and their slots cleared.  Everything is flushed every
-            // kKeepTiles tiles and at the end of the workgroup's stretch.
-            __syncthreads();
-            const bool flush_all = (t + 1 == t1) || ((t - t0 + 1) % kKeepTiles == 0);
-            if (tid == 0) nkeep = 0;
-            __syncthreads();
-            for (int i = tid; i < S; i += blockDim.x) {
-                if (tkey[i] == kEmptyRow) continue;
-                bool keep = false;
-                if (!flush_all && thits[i] >= kHotHits) keep = atomicAdd(&nkeep, 1u) < (uint32_t)(S / 4);
-                thits[i] = keep ? 0u : kFlushMark;
-            }
-            __syncthreads();
-            const int qr = a.rank >> 2;
-            for (int i = tid; i < S * qr; i += blockDim.x) {
-                const int slot = i / qr, part = i - slot * qr;
-                if (thits[slot] == kFlushMark) {
-                    double *tv = tv64 + (size_t)slot * TS + part * 4;
-                    const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                    global_add<FAST>(a, tkey[slot], part * 4, vv);
-                    tv[0] = 0.0;
-                    tv[1] = 0.0;
-                    tv[2] = 0.0;
-                    tv[3] = 0.0;
-                }
-            }
-            __syncthreads();
-            for (int i = tid; i < S; i += blockDim.x) {
-                if (thits[i] == kFlushMark) {
-                    tkey[i] = kEmptyRow;
-                    thits[i] = 0;
-                }
-            }
-            __syncthreads();
+        tile_end<FAST>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
+    }
+}
+
+// The specialised kernel's stretch (3 modes, one-word index, gathers
+// through 32-bit buffer offsets, FP32 atomics into the output), software
+// pipelined: the next batch is de-linearized, looked up and staged, and the
+// gathers of its next step issued, before the products and merges of the
+// current step -- so the gathers' latency overlaps this step's LDS work.  A
+// group stages a batch in one buffer of LPN x 4 words (value, destination,
+// the two other coordinates): every record of the previous batch is already
+// in registers when the next batch overwrites it (a wave's LDS operations
+// execute in order).  The two register sets of a step (X and Y) alternate
+// by hand, so nothing is copied.
+template <int LPN, typename FT, int TM>
+__device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep,
+                                           const uint64_t *lmask, uint64_t t0, uint64_t t1) {
+    constexpr int SB = LPN < 4 ? LPN : 4;  // records per step
+    constexpr int NS = LPN / SB;           // steps per batch
+    const int S = TM == 1 ? (1 << a.slots_log2) : (TM == 2 ? (int)a.dim_out : 0);
+    const int SK = TM == 1 ? S : 0;
+    const int TS = a.rank + 1;
+    uint32_t *tkey = smem;
+    uint32_t *thits = smem + SK;
+    const int TW = TM == 2 ? a.tw : 2;
+    void *tval = (void *)(smem + 2 * SK);
+    uint32_t *stage = smem + ((2 * SK + (size_t)TW * S * TS + 3) & ~(size_t)3);
+    const int tid = threadIdx.x;
+    const int q = tid & (LPN - 1);
+    const int grp = tid / LPN;
+    const int ngrp = blockDim.x / LPN;
+    uint32_t *gbuf = stage + grp * LPN * 4;
+    const int r0 = 4 * q;
+    const __amdgpu_buffer_rsrc_t rs0 = factor_rsrc(a.fac_other[0], a.fac_bytes[0]);
+    const __amdgpu_buffer_rsrc_t rs1 = factor_rsrc(a.fac_other[1], a.fac_bytes[1]);
+    const uint32_t ldb = a.ld * (uint32_t)sizeof(FT);
+    const uint32_t colb = (a.col0 + (uint32_t)r0) * (uint32_t)sizeof(FT);
+    const int mode = a.mode;
+
+    if (TM) {
+        for (int i = tid; i < SK; i += blockDim.x) {
+            tkey[i] = kEmptyRow;
+            thits[i] = 0;
         }
+        for (int i = tid; i < TW * S * TS; i += blockDim.x) smem[2 * SK + i] = 0u;
+        __syncthreads();
+    }
+
+    for (uint64_t t = t0; t < t1; t++) {
+        const uint64_t ts = t * a.tq + (t * a.tr) / a.ntiles;
+        const uint64_t te = (t + 1) * a.tq + ((t + 1) * a.tr) / a.ntiles;
+        const uint64_t per = (te - ts + ngrp - 1) / ngrp;
+        uint64_t ga = ts + (uint64_t)grp * per;
+        if (ga > te) ga = te;
+        const uint64_t gb = (ga + per < te) ? ga + per : te;
+        const uint64_t nsteps = (gb - ga + LPN - 1) / LPN * NS;
+
+        uint32_t cur = kEmptyRow;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        // index and value of this lane's nonzero in the next batch
+        uint64_t nlo = 0;
+        float nval = 0.f;
+        if (ga + q < gb) {
+            nlo = a.keys[ga + q];
+            nval = a.vals[ga + q];
+        }
+
+        // batch b: one nonzero per lane de-linearized, looked up, staged
+        auto decode = [&](uint64_t b) {
+            const uint64_t x = ga + b * LPN + q;
+            const uint64_t lo = nlo;
+            const float val = nval;
+            if (x + LPN < gb) {
+                nlo = a.keys[x + LPN];
+                nval = a.vals[x + LPN];
+            }
+            uint4 r = make_uint4(0u, kEmptyRow, 0u, 0u);
+            if (x < gb) {
+                uint32_t c[3];
+#pragma unroll
+                for (int m = 0; m < 3; m++) c[m] = (uint32_t)compress_lds(lo, lmask + 7 * m);
+                const uint32_t row = mode == 0 ? c[0] : (mode == 1 ? c[1] : c[2]);
+                // indices decode from valid coordinates; the check only keeps
+                // a corrupted index from reaching memory
+                if (row < a.dim_out) {
+                    uint32_t dst = row;
+                    if (TM == 1) {
+                        const uint32_t slot = table_slot(tkey, row, a.slots_log2);
+                        if (slot != kNoSlot) dst = kSlotBit | slot;
+                    } else if (TM == 2) {
+                        dst = kSlotBit | row;
+                    }
+                    r = make_uint4(__float_as_uint(val), dst, mode == 0 ? c[1] : c[0], mode == 2 ? c[1] : c[2]);
+                }
+            }
+            *(uint4 *)(gbuf + q * 4) = r;
+        };
+        // step k: its records' heads, and the gathers of both other modes
+        auto issue = [&](uint64_t k, float4 (&g0)[SB], float4 (&g1)[SB], uint32_t (&dv)[SB], float (&vv)[SB]) {
+            if (k % NS == 0) {
+                decode(k / NS);
+                __builtin_amdgcn_wave_barrier();
+            }
+            const uint32_t *buf = gbuf + (k % NS) * SB * 4;
+#pragma unroll
+            for (int s = 0; s < SB; s++) {
+                const uint4 h = *(const uint4 *)(buf + s * 4);
+                dv[s] = h.y;
+                vv[s] = __uint_as_float(h.x);
+                g0[s] = bload4<FT>(rs0, h.z * ldb + colb);
+                g1[s] = bload4<FT>(rs1, h.w * ldb + colb);
+            }
+        };
+        // products of a step, merged into runs of equal destinations
+        auto consume = [&](const float4 (&g0)[SB], const float4 (&g1)[SB], const uint32_t (&dv)[SB],
+                           const float (&vv)[SB]) {
+#pragma unroll
+            for (int s = 0; s < SB; s++) {
+                if (dv[s] == kEmptyRow) continue;
+                const float p[4] = {vv[s] * g0[s].x * g1[s].x, vv[s] * g0[s].y * g1[s].y,
+                                    vv[s] * g0[s].z * g1[s].z, vv[s] * g0[s].w * g1[s].w};
+                if (dv[s] == cur) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) acc[j] += p[j];
+                } else {
+                    if (cur != kEmptyRow) flush_run<TM, true>(a, tval, thits, cur, q, r0, acc);
+                    cur = dv[s];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) acc[j] = p[j];
+                }
+            }
+        };
+
+        float4 xg0[SB], xg1[SB], yg0[SB], yg1[SB];
+        uint32_t xd[SB], yd[SB];
+        float xv[SB], yv[SB];
+        if (nsteps > 0) issue(0, xg0, xg1, xd, xv);
+        for (uint64_t k = 0; k < nsteps; k += 2) {
+            if (k + 1 < nsteps) issue(k + 1, yg0, yg1, yd, yv);
+            consume(xg0, xg1, xd, xv);
+            if (k + 1 >= nsteps) break;
+            if (k + 2 < nsteps) issue(k + 2, xg0, xg1, xd, xv);
+            consume(yg0, yg1, yd, yv);
+        }
+        if (cur != kEmptyRow) flush_run<TM, true>(a, tval, thits, cur, q, r0, acc);
+        __builtin_amdgcn_wave_barrier();
+        tile_end<true>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
     }
 }
 
@@ -534,7 +688,8 @@ __global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
     }
     uint64_t t0, t1;
     stretch_of(a.ntiles, a.xcd_map, &t0, &t1);
-    mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
+    if constexpr (FAST) mttkrp_stretch_pipe<LPN, FT, TMC>(a, smem, nkeep, lmask, t0, t1);
+    else mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
 }
 
 // Many tensors in one persistent launch: the tiles of all jobs form one
@@ -660,8 +815,35 @@ DevProps &props(int dev);
 
 int device_cus(int dev) { return props(dev).cus; }
 
+// LDS words staged per nonzero: [value, destination, other coordinates]
+// rounded to 16 bytes.
+int record_words(int nmodes, int words) {
+    (void)words;
+    return (nmodes + 1 + 3) / 4 * 4;
+}
+
+size_t tile_plan_lds(const alto_tensor *h, int rank_tile, int slots, int threads) {
+    const size_t rec = (size_t)record_words(h->info.nmodes, h->info.index_words);
+    return (size_t)slots * (2 * (rank_tile + 1) + 2) * 4 + (size_t)threads * rec * 4 + 256;
+}
+
+bool tile_plan_fits(const alto_tensor *h, int rank_tile, int slots, int threads) {
+    return tile_plan_lds(h, rank_tile, slots, threads) <= props(h->device).lds;
+}
+
+alto_status check_launch_lds(const void *kern, size_t dyn, int dev) {
+    hipFuncAttributes fa;
+    size_t stat = 256;
+    if (hipFuncGetAttributes(&fa, kern) == hipSuccess) stat = fa.sharedSizeBytes;
+    else (void)hipGetLastError();
+    if (dyn + stat > props(dev).lds)
+        return fail(ALTO_ERR_ARG, "launch needs " + std::to_string(dyn + stat) + " bytes of LDS; the device has " +
+                                      std::to_string(props(dev).lds));
+    return ALTO_OK;
+}
+
 size_t direct_table_limit(const alto_tensor *h, int threads) {
-    const size_t rec = (size_t)((2 + h->info.nmodes - 1 + 3) & ~3);  // record words per nonzero
+    const size_t rec = (size_t)record_words(h->info.nmodes, h->info.index_words);
     const size_t stage = (size_t)threads * rec * 4 + 256;              // + static LDS and alignment
     const size_t lds = props(h->device).lds;
     return lds > stage ? lds - stage : 0;
@@ -804,8 +986,9 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
     if (p.conflict == ALTO_CR_TILE) {
         if (p.table_slots < 16 || (p.table_slots & (p.table_slots - 1)))
             return fail(ALTO_ERR_ARG, "table_slots must be a power of two >= 16");
-        const size_t lds = (size_t)p.table_slots * (2 * (rt + 1) + 2) * 4;  // FP64 row + key + hits
-        if (lds > 144 * 1024) return fail(ALTO_ERR_ARG, "LDS table too large for rank");
+        // FP64 rows + keys + hit counts, the record staging and static LDS
+        if (!tile_plan_fits(h, rt, p.table_slots, p.block_threads))
+            return fail(ALTO_ERR_ARG, "LDS table too large for rank and block size");
     }
     *out = p;
     return ALTO_OK;
@@ -885,7 +1068,7 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
     int l2 = 0;
     while ((1 << l2) < p.table_slots) l2++;
     a->slots_log2 = l2;
-    a->rec = ((h->info.nmodes + 1) + 3) / 4 * 4;
+    a->rec = record_words(h->info.nmodes, h->info.index_words);
     // whole-mode rows are FP64 when this rank tile fits so, else FP32
     a->tw = 2;
     if (a->tile_merge == 2 &&
@@ -957,6 +1140,9 @@ alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, in
     const int lpn = lpn_for(a.rank);
     const void *kern = pick_single(lpn, fdt, h->info.index_words, a);
     const size_t lds = lds_bytes(a, threads);
+    // never dispatch more LDS than a workgroup may hold
+    alto_status lst = check_launch_lds(kern, lds, h->device);
+    if (lst != ALTO_OK) return lst;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) {
         (void)hipGetLastError();
