@@ -346,10 +346,15 @@ def main():
     sweep_ms = ev[0].elapsed_time(ev[1])
     plans = [T.get_plan(n, rank, fdt) for n in range(X.nmodes)]
     f32_per_mode = None
+    bf16_err = None
     if fdt == alto.BF16:
-        # the same MTTKRPs with FP32 factors, for the precision comparison
-        f32_per_mode = []
+        # the same MTTKRPs with FP32 factors, for the precision comparison:
+        # time, and the relative Frobenius difference of the BF16-factor
+        # result from the FP32-factor one (the error BF16 storage adds)
+        f32_per_mode, bf16_err = [], []
         for n in range(X.nmodes):
+            T.mttkrp(n, mfacs, out=outs[n], rank=rank, fdt=fdt)
+            ob = outs[n].double()
             T.autotune(n, facs0, out=outs[n], rank=rank, fdt=alto.F32)
             ev[0].record()
             for _ in range(3):
@@ -357,6 +362,9 @@ def main():
             ev[1].record()
             torch.cuda.synchronize()
             f32_per_mode.append(ev[0].elapsed_time(ev[1]) / 3)
+            of = outs[n].double()
+            bf16_err.append(float((ob - of).norm() / of.norm()))
+            del ob, of
     T.free()
     torch.cuda.synchronize()
     tb = time.perf_counter()
@@ -409,6 +417,7 @@ def main():
             "sweep_ms": round(sweep_ms, 3),
             "mttkrp_only_gnnz_s": round(X.nnz * X.nmodes / (sum(per_mode) * 1e-3) / 1e9, 3),
             "fp32_factor_mttkrp_ms_per_mode": [round(x, 4) for x in f32_per_mode] if f32_per_mode else None,
+            "bf16_vs_fp32_factor_rel_err_per_mode": [float(f"{e:.3e}") for e in bf16_err] if bf16_err else None,
             "sweeps_per_step": nsweeps,
             "plans": plans,
         },
