@@ -326,17 +326,24 @@ def main():
     achieved = avg_bytes / (avg_launch_ms * 1e-3) / 1e9
     value = X.nnz * mttkrp_per_step / (ms_per_step * 1e-3) / 1e9
 
-    # phase breakdown (outside the timed region)
+    # phase breakdown (outside the timed region): each MTTKRP call timed
+    # alone with events, 3 warm-ups then 20 repetitions per mode
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     T = alto.AltoTensor(X.dims, coords, vals)
-    per_mode = []
+    per_mode, per_mode_pct = [], []
     for n in range(X.nmodes):
-        ev[0].record()
         for _ in range(3):
             T.mttkrp(n, mfacs, out=outs[n], rank=rank, fdt=fdt, plan=plan)
-        ev[1].record()
-        torch.cuda.synchronize()
-        per_mode.append(ev[0].elapsed_time(ev[1]) / 3)
+        reps = []
+        for _ in range(20):
+            ev[0].record()
+            T.mttkrp(n, mfacs, out=outs[n], rank=rank, fdt=fdt, plan=plan)
+            ev[1].record()
+            torch.cuda.synchronize()
+            reps.append(ev[0].elapsed_time(ev[1]))
+        p10, p50, p90 = np.percentile(reps, [10, 50, 90])
+        per_mode.append(float(p50))
+        per_mode_pct.append([round(float(p10), 4), round(float(p90), 4)])
     for w, f in zip(work, facs0):
         w.copy_(f)
     ev[0].record()
@@ -344,6 +351,35 @@ def main():
     ev[1].record()
     torch.cuda.synchronize()
     sweep_ms = ev[0].elapsed_time(ev[1])
+    # the same sweep captured once in a HIP graph and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        T.sweep(work, lam=lam, fdt=fdt)
+    torch.cuda.synchronize()
+    greps = []
+    for _ in range(5):
+        ev[0].record()
+        graph.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        greps.append(ev[0].elapsed_time(ev[1]))
+    sweep_graph_ms = float(np.median(greps))
+    del graph
+    # a plain device copy of 1 GiB: the HBM bandwidth this GPU reaches in practice
+    src = torch.empty(2**28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    creps = []
+    for _ in range(5):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        creps.append(ev[0].elapsed_time(ev[1]))
+    copy_gbs = 2 * src.numel() * 4 / (float(np.median(creps)) * 1e-3) / 1e9
+    del src, dst
     plans = [T.get_plan(n, rank, fdt) for n in range(X.nmodes)]
     f32_per_mode = None
     bf16_err = None
@@ -373,6 +409,9 @@ def main():
     build_ms = (time.perf_counter() - tb) * 1e3
     T.free()
 
+    comp_bytes = [X.nnz * (8 * info_words + 4) + sum(X.dims[m] * rank * fbytes for m in range(X.nmodes) if m != n)
+                  + X.dims[n] * rank * 4 for n in range(X.nmodes)]
+    alto_bytes = X.nnz * (8 * info_words + 4)
     workload = f"{args.config}" + (f"-nnz{X.nnz}" if args.nnz else "")
     traffic = traffic_for(workload)
     out = {
@@ -410,12 +449,21 @@ def main():
             "avg_launch_ms": round(avg_launch_ms, 5),
             "launches_per_mttkrp": round(launches / calls, 3),
             "kernel_sha": kernel_hash(),
+            "measured_copy_gbs": round(copy_gbs, 1),
+            # index + value once, every other factor once, the output once
+            "compulsory_bytes_per_mode": comp_bytes,
+            "compulsory_ms_at_peak_per_mode": [round(b / HBM_PEAK_GBS / 1e6, 4) for b in comp_bytes],
         },
         "breakdown": {
             "build_ms": round(build_ms, 3),
+            # ALTO (index words + FP32 value) against COO with int64 / int32 coordinates
+            "alto_over_coo_bytes": [round(alto_bytes / (X.nnz * (8 * X.nmodes + 4)), 4),
+                                    round(alto_bytes / (X.nnz * (4 * X.nmodes + 4)), 4)],
             "mttkrp_call_ms_per_mode": [round(x, 4) for x in per_mode],
             "sweep_ms": round(sweep_ms, 3),
             "mttkrp_only_gnnz_s": round(X.nnz * X.nmodes / (sum(per_mode) * 1e-3) / 1e9, 3),
+            "mttkrp_call_ms_p10_p90_per_mode": per_mode_pct,
+            "sweep_graph_replay_ms": round(sweep_graph_ms, 3),
             "fp32_factor_mttkrp_ms_per_mode": [round(x, 4) for x in f32_per_mode] if f32_per_mode else None,
             "bf16_vs_fp32_factor_rel_err_per_mode": [float(f"{e:.3e}") for e in bf16_err] if bf16_err else None,
             "sweeps_per_step": nsweeps,
