@@ -226,13 +226,18 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
     for (int rt : {rank / 2, rank / 4}) {
         if (rt < 8 || rt % 4 || rank % rt) continue;
         for (int tile : {4096, 16384}) {
-            alto_mttkrp_plan p = base;
-            p.conflict = ALTO_CR_TILE;
-            p.tile_nnz = tile;
-            p.rank_tile = rt;
-            p.table_slots = std::max(64, pow2_floor(8192 / rt));
-            if (!tile_plan_fits(h, rt, p.table_slots, p.block_threads)) continue;
-            cands.push_back(p);
+            for (int threads : {256, 512}) {
+                for (int f : {1, 2}) {
+                    alto_mttkrp_plan p = base;
+                    p.conflict = ALTO_CR_TILE;
+                    p.tile_nnz = tile;
+                    p.rank_tile = rt;
+                    p.block_threads = threads;
+                    p.table_slots = std::max(64, pow2_floor(8192 / rt) * f);
+                    if (!tile_plan_fits(h, rt, p.table_slots, threads)) continue;
+                    cands.push_back(p);
+                }
+            }
         }
     }
     // the whole mode in LDS, for short modes
