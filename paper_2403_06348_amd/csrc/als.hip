@@ -6,12 +6,12 @@
 // FP64; the I x R matrices are FP32 (FP64 arithmetic, FP32 storage).
 //
 // Kernels
-//   k_gram_partial   partial Grams A^T A of row chunks (FP64 accumulation)
+//   k_gram_rows      partial Grams A^T A of row chunks (FP64 accumulation)
 //   k_gram_reduce    sum of the partials (fixed order, deterministic)
 //   k_als_prepare    one workgroup: V, Cholesky V = L L^T, W = L^-T L^-1;
 //                    if a pivot is at rounding level, W = pseudo-inverse from
 //                    a cyclic Jacobi eigendecomposition (flag bit n set)
-//   k_als_apply      A^(n) = M W row by row, plus partial Grams of A^(n)
+//   k_gram_rows<.., true>  A^(n) = M W row by row, plus partial Grams of A^(n)
 //   k_als_finalize   lambda_r = sqrt(G_rr), Gram of the normalized factor
 //   k_als_normalize  A^(n)(:, r) /= lambda_r, BF16 shadow refresh
 #include <math.h>
@@ -30,7 +30,6 @@ namespace alto {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kChunk = 32;        // rows staged per step
 constexpr int kPartials = 512;    // partial Gram blocks
 constexpr int kMaxSweepRank = 64;
 constexpr uint64_t kBatchAloneNnz = uint64_t(1) << 21;  // a job this large fills the GPU alone
@@ -42,44 +41,125 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
     return (uint16_t)(r >> 16);
 }
 
-// Accumulate sum_i X[i][r] X[i][s] over rows staged in LDS (double).
-template <int ENT>
-__device__ inline void gram_accumulate(const double *sx, int rows, int R, const int *re, const int *se, double *acc) {
-    for (int i = 0; i < rows; i++) {
-        const double *x = sx + i * R;
+// Partial Grams over row chunks, register-tiled.  A block stages 256
+// consecutive rows (FP32, one per thread) in LDS; for APPLY it first forms
+// each row of A = M W (thread per row, FP64 accumulation, W read from LDS
+// as broadcasts), stores it as FP32 to A and back into LDS.  Then every
+// thread accumulates one 4 x 4 tile of sum_i a_i a_i^T over its share of
+// the chunk's rows in FP64.  At the end the row groups' tiles are added in
+// a fixed order and the block writes its partial R x R Gram.
+// RB: rank bucket (8, 16, 32, 64), R <= RB, R a multiple of 4.
+template <int RB, bool APPLY>
+__global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict__ src, const double *__restrict__ W,
+                                                        float *__restrict__ A, uint64_t I, int R,
+                                                        double *__restrict__ partials) {
+    constexpr int STR = RB + 4;             // LDS row stride (floats), 16-byte aligned
+    constexpr int TPR = RB / 4;             // 4 x 4 tiles per Gram row
+    constexpr int TB = TPR * TPR;           // tiles of the Gram
+    constexpr int G = kThreads / TB;        // row groups
+    constexpr int SA = kThreads * STR > 8192 ? kThreads * STR : 8192;  // floats; >= 32 KiB for the tile sums
+    __shared__ __align__(16) float sa[SA];
+    __shared__ __align__(16) double sw[APPLY ? RB * RB : 1];
+    const int tid = threadIdx.x;
+    const int t = tid % TB, g = tid / TB;
+    const int tr = t / TPR, ts = t % TPR;
+    const bool tile_ok = 4 * tr < R && 4 * ts < R;
+    if (APPLY)
+        for (int e = tid; e < R * R; e += kThreads) sw[(e / R) * RB + e % R] = W[e];
+    double acc[4][4];
 #pragma unroll
-        for (int j = 0; j < ENT; j++)
-            if (re[j] >= 0) acc[j] = fma(x[re[j]], x[se[j]], acc[j]);
-    }
-}
-
-template <int ENT>
-__global__ __launch_bounds__(kThreads) void k_gram_partial(const float *__restrict__ A, uint64_t I, int R,
-                                                           double *__restrict__ partials) {
-    __shared__ double sx[kChunk * kMaxSweepRank];
-    int re[ENT], se[ENT];
-    double acc[ENT];
+    for (int x = 0; x < 4; x++)
 #pragma unroll
-    for (int j = 0; j < ENT; j++) {
-        const int e = threadIdx.x + j * kThreads;
-        re[j] = e < R * R ? e / R : -1;
-        se[j] = e < R * R ? e % R : 0;
-        acc[j] = 0.0;
-    }
+        for (int y = 0; y < 4; y++) acc[x][y] = 0.0;
     const uint64_t per = (I + gridDim.x - 1) / gridDim.x;
     const uint64_t a = (uint64_t)blockIdx.x * per;
     const uint64_t b = a + per < I ? a + per : I;
-    for (uint64_t c = a; c < b; c += kChunk) {
-        const int rows = (int)((b - c) < (uint64_t)kChunk ? (b - c) : (uint64_t)kChunk);
-        for (int t = threadIdx.x; t < rows * R; t += kThreads) sx[t] = (double)A[c * R + t];
+    const int q4 = R / 4;
+    for (uint64_t c = a; c < b; c += kThreads) {
+        const int rows = (int)((b - c) < (uint64_t)kThreads ? (b - c) : (uint64_t)kThreads);
         __syncthreads();
-        gram_accumulate<ENT>(sx, rows, R, re, se, acc);
+        const float4 *s4 = (const float4 *)(src + c * R);
+        for (int v = tid; v < rows * q4; v += kThreads) {
+            const int row = v / q4, q = v - row * q4;
+            *(float4 *)(sa + row * STR + 4 * q) = s4[v];
+        }
         __syncthreads();
-    }
-    double *o = partials + (uint64_t)blockIdx.x * R * R;
+        if (APPLY && tid < rows) {
+            float m[RB];
 #pragma unroll
-    for (int j = 0; j < ENT; j++)
-        if (re[j] >= 0) o[re[j] * R + se[j]] = acc[j];
+            for (int k = 0; k < RB; k += 4) {
+                const float4 v = k < R ? *(const float4 *)(sa + tid * STR + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+                m[k] = v.x;
+                m[k + 1] = v.y;
+                m[k + 2] = v.z;
+                m[k + 3] = v.w;
+            }
+            // output columns in blocks of at most 32 (FP64 accumulators),
+            // the rank loop unrolled over the bucket so that m stays in
+            // registers
+            constexpr int CB = RB < 32 ? RB : 32;
+            float4 *dst = (float4 *)(A + (c + tid) * R);
+#pragma unroll
+            for (int j0 = 0; j0 < RB; j0 += CB) {
+                if (j0 < R) {
+                    double o[CB];
+#pragma unroll
+                    for (int j = 0; j < CB; j++) o[j] = 0.0;
+#pragma unroll
+                    for (int k = 0; k < RB; k++) {
+                        if (k < R) {
+                            const double mk = (double)m[k];
+                            const double *wk = sw + k * RB + j0;
+#pragma unroll
+                            for (int j = 0; j < CB; j += 2) {
+                                if (j0 + j < R) {
+                                    const double2 w2 = *(const double2 *)(wk + j);
+                                    o[j] = fma(mk, w2.x, o[j]);
+                                    o[j + 1] = fma(mk, w2.y, o[j + 1]);
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < CB; j += 4) {
+                        if (j0 + j < R) {
+                            const float4 f = make_float4((float)o[j], (float)o[j + 1], (float)o[j + 2], (float)o[j + 3]);
+                            dst[(j0 + j) / 4] = f;
+                            *(float4 *)(sa + tid * STR + j0 + j) = f;
+                        }
+                    }
+                }
+            }
+        }
+        if (APPLY) __syncthreads();
+        if (tile_ok) {
+            for (int i = g; i < rows; i += G) {
+                const float4 x = *(const float4 *)(sa + i * STR + 4 * tr);
+                const float4 y = *(const float4 *)(sa + i * STR + 4 * ts);
+                const double xv[4] = {x.x, x.y, x.z, x.w}, yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+#pragma unroll
+                    for (int w = 0; w < 4; w++) acc[u][w] = fma(xv[u], yv[w], acc[u][w]);
+            }
+        }
+    }
+    __syncthreads();
+    // tile sums of the row groups, then their fixed-order total per entry
+    double *red = (double *)sa;  // G x TB x 16 doubles = 32 KiB
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int w = 0; w < 4; w++) red[((size_t)g * TB + t) * 16 + u * 4 + w] = acc[u][w];
+    __syncthreads();
+    double *o = partials + (uint64_t)blockIdx.x * R * R;
+    for (int e = tid; e < R * R; e += kThreads) {
+        const int r = e / R, c2 = e % R;
+        const int tt = (r / 4) * TPR + c2 / 4, pos = (r % 4) * 4 + c2 % 4;
+        double sum = 0.0;
+        for (int k = 0; k < G; k++) sum += red[((size_t)k * TB + tt) * 16 + pos];
+        o[e] = sum;
+    }
 }
 
 // G = sum of the np partial R x R blocks.  Block b owns entries
@@ -251,50 +331,6 @@ __global__ __launch_bounds__(kThreads) void k_als_prepare(const double *__restri
     }
 }
 
-// A = M W (FP64 arithmetic, FP32 store) and partial Grams of the stored A.
-template <int ENT>
-__global__ __launch_bounds__(kThreads) void k_als_apply(const float *__restrict__ M, const double *__restrict__ W,
-                                                        float *__restrict__ A, uint64_t I, int R,
-                                                        double *__restrict__ partials) {
-    __shared__ double sw[kMaxSweepRank * kMaxSweepRank];
-    __shared__ double sm[kChunk * kMaxSweepRank];
-    __shared__ double sa[kChunk * kMaxSweepRank];
-    for (int e = threadIdx.x; e < R * R; e += kThreads) sw[e] = W[e];
-    int re[ENT], se[ENT];
-    double acc[ENT];
-#pragma unroll
-    for (int j = 0; j < ENT; j++) {
-        const int e = threadIdx.x + j * kThreads;
-        re[j] = e < R * R ? e / R : -1;
-        se[j] = e < R * R ? e % R : 0;
-        acc[j] = 0.0;
-    }
-    const uint64_t per = (I + gridDim.x - 1) / gridDim.x;
-    const uint64_t a = (uint64_t)blockIdx.x * per;
-    const uint64_t b = a + per < I ? a + per : I;
-    __syncthreads();
-    for (uint64_t c = a; c < b; c += kChunk) {
-        const int rows = (int)((b - c) < (uint64_t)kChunk ? (b - c) : (uint64_t)kChunk);
-        for (int t = threadIdx.x; t < rows * R; t += kThreads) sm[t] = (double)M[c * R + t];
-        __syncthreads();
-        for (int t = threadIdx.x; t < rows * R; t += kThreads) {
-            const int i = t / R, s = t % R;
-            double v = 0.0;
-            for (int r = 0; r < R; r++) v = fma(sm[i * R + r], sw[r * R + s], v);
-            const float f = (float)v;
-            A[c * R + t] = f;
-            sa[t] = (double)f;
-        }
-        __syncthreads();
-        gram_accumulate<ENT>(sa, rows, R, re, se, acc);
-        __syncthreads();
-    }
-    double *o = partials + (uint64_t)blockIdx.x * R * R;
-#pragma unroll
-    for (int j = 0; j < ENT; j++)
-        if (re[j] >= 0) o[re[j] * R + se[j]] = acc[j];
-}
-
 // Gn holds the Gram of the updated (unnormalized) factor: lambda = the
 // column norms, then Gn is rescaled in place to the normalized factor's Gram.
 __global__ __launch_bounds__(kThreads) void k_als_finalize(double *__restrict__ Gn, int R, double *__restrict__ lam_ws,
@@ -332,21 +368,19 @@ __global__ void k_to_bf16(const float *__restrict__ A, uint64_t n, uint16_t *__r
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) out[t] = f32_to_bf16_rne(A[t]);
 }
 
-int ent_for(int R) {
-    const int e = (R * R + kThreads - 1) / kThreads;
-    int p = 1;
-    while (p < e) p <<= 1;
-    return p;
-}
+// Rank bucket of the register-tiled Gram kernels.
+int rank_bucket(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64; }
 
-#define ALTO_ENT_DISPATCH(ent, KERNEL, ...)                                               \
-    switch (ent) {                                                                        \
-        case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                        \
-        case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                        \
-        case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                        \
-        case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                        \
-        default: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                      \
+template <bool APPLY>
+void launch_gram_rows(int R, unsigned P, hipStream_t s, const float *src, const double *W, float *A, uint64_t I,
+                      double *partials) {
+    switch (rank_bucket(R)) {
+        case 8: hipLaunchKernelGGL((k_gram_rows<8, APPLY>), dim3(P), dim3(kThreads), 0, s, src, W, A, I, R, partials); break;
+        case 16: hipLaunchKernelGGL((k_gram_rows<16, APPLY>), dim3(P), dim3(kThreads), 0, s, src, W, A, I, R, partials); break;
+        case 32: hipLaunchKernelGGL((k_gram_rows<32, APPLY>), dim3(P), dim3(kThreads), 0, s, src, W, A, I, R, partials); break;
+        default: hipLaunchKernelGGL((k_gram_rows<64, APPLY>), dim3(P), dim3(kThreads), 0, s, src, W, A, I, R, partials); break;
     }
+}
 
 unsigned partial_blocks(uint64_t I) {
     uint64_t p = (I + 255) / 256;
@@ -388,12 +422,11 @@ alto_status sweep_begin(alto_tensor *h, int rank, int fdt, float *const *factors
     }
     double *grams = (double *)h->ws_sweep;
     double *partials = grams + N * rr + rr;
-    const int ent = ent_for(R);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, h->ws_flags, (uint64_t)1, 0u);
     for (int m = 0; m < N; m++) {
         const uint64_t I = h->info.dims[m];
         const unsigned P = partial_blocks(I);
-        ALTO_ENT_DISPATCH(ent, k_gram_partial, dim3(P), dim3(kThreads), 0, s, factors[m], I, R, partials);
+        launch_gram_rows<false>(R, P, s, factors[m], nullptr, nullptr, I, partials);
         hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(R)), dim3(kThreads), 0, s, partials, (int)P, R,
                            grams + m * rr);
         if (fdt == ALTO_BF16)
@@ -429,8 +462,7 @@ alto_status sweep_post(alto_tensor *h, int n, int rank, int fdt, float *const *f
     double *lam_ws = partials + (size_t)kPartials * rr;
     const uint64_t I = h->info.dims[n];
     const unsigned P = partial_blocks(I);
-    const int ent = ent_for(R);
-    ALTO_ENT_DISPATCH(ent, k_als_apply, dim3(P), dim3(kThreads), 0, s, h->ws_m, W, factors[n], I, R, partials);
+    launch_gram_rows<true>(R, P, s, h->ws_m, W, factors[n], I, partials);
     hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(R)), dim3(kThreads), 0, s, partials, (int)P, R,
                        grams + n * rr);
     hipLaunchKernelGGL(k_als_finalize, dim3(1), dim3(kThreads), 0, s, grams + n * rr, R, lam_ws, lambda);
