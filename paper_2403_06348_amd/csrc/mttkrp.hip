@@ -514,37 +514,81 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
     }
 }
 
-// The specialised kernel's stretch (3 modes, one-word index, gathers
-// through 32-bit buffer offsets, FP32 atomics into the output), software
-// pipelined: the next batch is de-linearized, looked up and staged, and the
-// gathers of its next step issued, before the products and merges of the
-// current step -- so the gathers' latency overlaps this step's LDS work.  A
-// group stages a batch in one buffer of LPN x 4 words (value, destination,
-// the two other coordinates): every record of the previous batch is already
-// in registers when the next batch overwrites it (a wave's LDS operations
-// execute in order).  The two register sets of a step (X and Y) alternate
-// by hand, so nothing is copied.
-template <int LPN, typename FT, int TM>
+// Extraction masks of every mode in LDS, per mode kMaskStride words: for
+// each index word the AND mask and the 6 move masks, then (two-word
+// indices) the number of the mode's bits held in word 0.  All lanes read the
+// same address, so every read is a broadcast.
+constexpr int kMaskStride = 15;
+constexpr int kMaskWords = ALTO_MAX_MODES * kMaskStride;
+
+// Fill `lm` from the plan (all threads of the block call it; ends with a
+// barrier).
+__device__ inline void load_masks(const LinePlan &lp, int nmodes, uint64_t *lm) {
+    for (int i = threadIdx.x; i < nmodes * kMaskStride; i += blockDim.x) {
+        const int m = i / kMaskStride, k = i - m * kMaskStride;
+        const ModeMasks &mm = lp.mode[m];
+        uint64_t v;
+        if (k < 14) {
+            const WordMasks &w = mm.w[k / 7];
+            v = k % 7 == 0 ? w.mask : w.mv[k % 7 - 1];
+        } else {
+            v = (uint64_t)mm.lo_bits;
+        }
+        lm[i] = v;
+    }
+    __syncthreads();
+}
+
+// Coordinate of mode m from an index (lo, hi) with the masks in LDS.
+template <int WORDS>
+__device__ inline uint32_t extract_lds(const uint64_t *lm, int m, uint64_t lo, uint64_t hi) {
+    const uint64_t *mm = lm + m * kMaskStride;
+    uint64_t c = compress_lds(lo, mm);
+    if (WORDS == 2) c |= compress_lds(hi, mm + 7) << (uint32_t)mm[14];
+    return (uint32_t)c;
+}
+
+// Software-pipelined stretch for tensors of up to 5 modes (MAXO = most
+// other modes: 2 or 4): the next batch is de-linearized, looked up and
+// staged, and the gathers of its next step issued, before the products and
+// merges of the current step -- so the gathers' latency overlaps this
+// step's LDS work.  A group stages a batch in one buffer of LPN records of
+// RW words (value, destination, the other coordinates): every record of the
+// previous batch is already in registers when the next batch overwrites it
+// (a wave's LDS operations execute in order).  The two register sets of a
+// step (X and Y) alternate by hand, so nothing is copied.  FAST: exactly 3
+// modes, one-word index, 32-bit buffer gathers and FP32 atomics into the
+// output (the specialised kernel).
+template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST>
 __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep,
                                            const uint64_t *lmask, uint64_t t0, uint64_t t1) {
-    constexpr int SB = LPN < 4 ? LPN : 4;  // records per step
-    constexpr int NS = LPN / SB;           // steps per batch
+    static_assert(MAXO == 2 || MAXO == 4, "pipelined stretch: up to 5 modes");
+    const int TM = TMC >= 0 ? TMC : a.tile_merge;
+    constexpr int SB = MAXO == 2 ? (LPN < 4 ? LPN : 4) : (LPN < 2 ? LPN : 2);  // records per step
+    constexpr int NS = LPN / SB;                                               // steps per batch
+    constexpr int RW = MAXO == 2 ? 4 : 8;                                      // record words
+    const int nmodes = FAST ? 3 : a.nmodes;
+    const int nother = nmodes - 1;
     const int S = TM == 1 ? (1 << a.slots_log2) : (TM == 2 ? (int)a.dim_out : 0);
     const int SK = TM == 1 ? S : 0;
     const int TS = a.rank + 1;
     uint32_t *tkey = smem;
     uint32_t *thits = smem + SK;
-    const int TW = TM == 2 ? a.tw : 2;
+    const int TW = a.tw;
     void *tval = (void *)(smem + 2 * SK);
     uint32_t *stage = smem + ((2 * SK + (size_t)TW * S * TS + 3) & ~(size_t)3);
     const int tid = threadIdx.x;
     const int q = tid & (LPN - 1);
     const int grp = tid / LPN;
     const int ngrp = blockDim.x / LPN;
-    uint32_t *gbuf = stage + grp * LPN * 4;
+    uint32_t *gbuf = stage + grp * LPN * RW;
     const int r0 = 4 * q;
-    const __amdgpu_buffer_rsrc_t rs0 = factor_rsrc(a.fac_other[0], a.fac_bytes[0]);
-    const __amdgpu_buffer_rsrc_t rs1 = factor_rsrc(a.fac_other[1], a.fac_bytes[1]);
+    const bool ract = r0 < a.rank;
+    const bool buf32 = FAST || a.buf32;
+    __amdgpu_buffer_rsrc_t rs[MAXO];
+#pragma unroll
+    for (int k = 0; k < MAXO; k++)
+        if (k < nother) rs[k] = factor_rsrc(a.fac_other[k], a.fac_bytes[k]);
     const uint32_t ldb = a.ld * (uint32_t)sizeof(FT);
     const uint32_t colb = (a.col0 + (uint32_t)r0) * (uint32_t)sizeof(FT);
     const int mode = a.mode;
@@ -570,28 +614,36 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
         uint32_t cur = kEmptyRow;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         // index and value of this lane's nonzero in the next batch
-        uint64_t nlo = 0;
+        uint64_t nlo = 0, nhi = 0;
         float nval = 0.f;
         if (ga + q < gb) {
-            nlo = a.keys[ga + q];
+            nlo = a.keys[(ga + q) * WORDS];
+            if (WORDS == 2) nhi = a.keys[(ga + q) * WORDS + 1];
             nval = a.vals[ga + q];
         }
 
         // batch b: one nonzero per lane de-linearized, looked up, staged
         auto decode = [&](uint64_t b) {
             const uint64_t x = ga + b * LPN + q;
-            const uint64_t lo = nlo;
+            const uint64_t lo = nlo, hi = nhi;
             const float val = nval;
             if (x + LPN < gb) {
-                nlo = a.keys[x + LPN];
+                nlo = a.keys[(x + LPN) * WORDS];
+                if (WORDS == 2) nhi = a.keys[(x + LPN) * WORDS + 1];
                 nval = a.vals[x + LPN];
             }
-            uint4 r = make_uint4(0u, kEmptyRow, 0u, 0u);
-            if (x < gb) {
-                uint32_t c[3];
+            uint32_t r[RW];
 #pragma unroll
-                for (int m = 0; m < 3; m++) c[m] = (uint32_t)compress_lds(lo, lmask + 7 * m);
-                const uint32_t row = mode == 0 ? c[0] : (mode == 1 ? c[1] : c[2]);
+            for (int k = 0; k < RW; k++) r[k] = 0u;
+            r[1] = kEmptyRow;
+            if (x < gb) {
+                uint32_t c[MAXO + 1];
+#pragma unroll
+                for (int m = 0; m <= MAXO; m++) c[m] = m < nmodes ? extract_lds<WORDS>(lmask, m, lo, hi) : 0u;
+                uint32_t row = c[0];
+#pragma unroll
+                for (int m = 1; m <= MAXO; m++)
+                    if (m == mode) row = c[m];
                 // indices decode from valid coordinates; the check only keeps
                 // a corrupted index from reaching memory
                 if (row < a.dim_out) {
@@ -602,40 +654,64 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
                     } else if (TM == 2) {
                         dst = kSlotBit | row;
                     }
-                    r = make_uint4(__float_as_uint(val), dst, mode == 0 ? c[1] : c[0], mode == 2 ? c[1] : c[2]);
+                    r[0] = __float_as_uint(val);
+                    r[1] = dst;
+#pragma unroll
+                    for (int k = 0; k < MAXO; k++) r[2 + k] = k < mode ? c[k] : c[k + 1];
                 }
             }
-            *(uint4 *)(gbuf + q * 4) = r;
+            uint32_t *rec = gbuf + q * RW;
+            *(uint4 *)rec = make_uint4(r[0], r[1], r[2], r[3]);
+            if (RW == 8) *(uint4 *)(rec + 4) = make_uint4(r[4], r[5], r[6], r[7]);
         };
-        // step k: its records' heads, and the gathers of both other modes
-        auto issue = [&](uint64_t k, float4 (&g0)[SB], float4 (&g1)[SB], uint32_t (&dv)[SB], float (&vv)[SB]) {
+        // step k: its records' heads, and the gathers of the other modes
+        auto issue = [&](uint64_t k, float4 (&g)[MAXO][SB], uint32_t (&dv)[SB], float (&vv)[SB]) {
             if (k % NS == 0) {
                 decode(k / NS);
                 __builtin_amdgcn_wave_barrier();
             }
-            const uint32_t *buf = gbuf + (k % NS) * SB * 4;
+            const uint32_t *buf = gbuf + (k % NS) * SB * RW;
 #pragma unroll
             for (int s = 0; s < SB; s++) {
-                const uint4 h = *(const uint4 *)(buf + s * 4);
+                const uint4 h = *(const uint4 *)(buf + s * RW);
+                const uint4 h2 = RW == 8 ? *(const uint4 *)(buf + s * RW + 4) : make_uint4(0u, 0u, 0u, 0u);
                 dv[s] = h.y;
                 vv[s] = __uint_as_float(h.x);
-                g0[s] = bload4<FT>(rs0, h.z * ldb + colb);
-                g1[s] = bload4<FT>(rs1, h.w * ldb + colb);
+                const uint32_t idx[4] = {h.z, h.w, h2.x, h2.y};
+#pragma unroll
+                for (int k2 = 0; k2 < MAXO; k2++) {
+                    if (k2 < nother) {
+                        if (buf32) {
+                            g[k2][s] = bload4<FT>(rs[k2], idx[k2] * ldb + colb);
+                        } else {
+                            const uint32_t ii = min(idx[k2], a.last_other[k2]);
+                            g[k2][s] = ract ? load4<FT>(a.fac_other[k2], (uint64_t)ii * a.ld + a.col0 + r0)
+                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+                        }
+                    }
+                }
             }
         };
         // products of a step, merged into runs of equal destinations
-        auto consume = [&](const float4 (&g0)[SB], const float4 (&g1)[SB], const uint32_t (&dv)[SB],
-                           const float (&vv)[SB]) {
+        auto consume = [&](const float4 (&g)[MAXO][SB], const uint32_t (&dv)[SB], const float (&vv)[SB]) {
 #pragma unroll
             for (int s = 0; s < SB; s++) {
                 if (dv[s] == kEmptyRow) continue;
-                const float p[4] = {vv[s] * g0[s].x * g1[s].x, vv[s] * g0[s].y * g1[s].y,
-                                    vv[s] * g0[s].z * g1[s].z, vv[s] * g0[s].w * g1[s].w};
+                float p[4] = {vv[s], vv[s], vv[s], vv[s]};
+#pragma unroll
+                for (int k2 = 0; k2 < MAXO; k2++) {
+                    if (k2 < nother) {
+                        p[0] *= g[k2][s].x;
+                        p[1] *= g[k2][s].y;
+                        p[2] *= g[k2][s].z;
+                        p[3] *= g[k2][s].w;
+                    }
+                }
                 if (dv[s] == cur) {
 #pragma unroll
                     for (int j = 0; j < 4; j++) acc[j] += p[j];
                 } else {
-                    if (cur != kEmptyRow) flush_run<TM, true>(a, tval, thits, cur, q, r0, acc);
+                    if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
                     cur = dv[s];
 #pragma unroll
                     for (int j = 0; j < 4; j++) acc[j] = p[j];
@@ -643,20 +719,20 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
             }
         };
 
-        float4 xg0[SB], xg1[SB], yg0[SB], yg1[SB];
+        float4 xg[MAXO][SB], yg[MAXO][SB];
         uint32_t xd[SB], yd[SB];
         float xv[SB], yv[SB];
-        if (nsteps > 0) issue(0, xg0, xg1, xd, xv);
+        if (nsteps > 0) issue(0, xg, xd, xv);
         for (uint64_t k = 0; k < nsteps; k += 2) {
-            if (k + 1 < nsteps) issue(k + 1, yg0, yg1, yd, yv);
-            consume(xg0, xg1, xd, xv);
+            if (k + 1 < nsteps) issue(k + 1, yg, yd, yv);
+            consume(xg, xd, xv);
             if (k + 1 >= nsteps) break;
-            if (k + 2 < nsteps) issue(k + 2, xg0, xg1, xd, xv);
-            consume(yg0, yg1, yd, yv);
+            if (k + 2 < nsteps) issue(k + 2, xg, xd, xv);
+            consume(yg, yd, yv);
         }
-        if (cur != kEmptyRow) flush_run<TM, true>(a, tval, thits, cur, q, r0, acc);
+        if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
         __builtin_amdgcn_wave_barrier();
-        tile_end<true>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
+        tile_end<FAST>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
     }
 }
 
@@ -676,30 +752,29 @@ template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST>
 __global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ uint32_t nkeep;
-    __shared__ uint64_t lmask[FAST ? 21 : 1];
-    if (FAST) {
-        // the 3 modes' extraction masks: the AND mask, then the 6 move masks
-        const int i = threadIdx.x;
-        if (i < 21) {
-            const WordMasks &w = a.lp.mode[i / 7].w[0];
-            lmask[i] = i % 7 == 0 ? w.mask : w.mv[i % 7 - 1];
-        }
-        __syncthreads();
-    }
+    __shared__ uint64_t lmask[FAST ? kMaskWords : 1];
     uint64_t t0, t1;
     stretch_of(a.ntiles, a.xcd_map, &t0, &t1);
-    if constexpr (FAST) mttkrp_stretch_pipe<LPN, FT, TMC>(a, smem, nkeep, lmask, t0, t1);
-    else mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
+    // single launches: the pipelined loop for the specialised case; for
+    // other shapes it measured slower than the plain loop (more registers
+    // and scalar state per step), while it pays in the batched launches
+    if constexpr (FAST) {
+        load_masks(a.lp, a.nmodes, lmask);
+        mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
+    } else {
+        mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
+    }
 }
 
 // Many tensors in one persistent launch: the tiles of all jobs form one
 // list (prefix[j] = first tile of job j); each workgroup drains a balanced
 // stretch of it, crossing job boundaries.
 template <int LPN, typename FT, int WORDS, int MAXO>
-__global__ __launch_bounds__(256) void k_mttkrp_batch(const MttkrpArgs *__restrict__ jobs,
+__global__ __launch_bounds__(256, 2) void k_mttkrp_batch(const MttkrpArgs *__restrict__ jobs,
                                                       const uint64_t *__restrict__ prefix, int njobs, int xcd_map) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ uint32_t nkeep;
+    __shared__ uint64_t lmask[MAXO <= 4 ? kMaskWords : 1];
     uint64_t g0, g1;
     stretch_of(prefix[njobs], xcd_map, &g0, &g1);
     // first job whose tiles reach past g0
@@ -713,7 +788,12 @@ __global__ __launch_bounds__(256) void k_mttkrp_batch(const MttkrpArgs *__restri
         const uint64_t a0 = prefix[j], a1 = prefix[j + 1];
         const uint64_t t0 = (g0 > a0 ? g0 : a0) - a0, t1 = (g1 < a1 ? g1 : a1) - a0;
         if (t0 < t1) {
-            mttkrp_stretch<LPN, FT, WORDS, MAXO, -1, false>(jobs[j], smem, nkeep, nullptr, t0, t1);
+            if constexpr (MAXO <= 4) {
+                load_masks(jobs[j].lp, jobs[j].nmodes, lmask);
+                mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, -1, false>(jobs[j], smem, nkeep, lmask, t0, t1);
+            } else {
+                mttkrp_stretch<LPN, FT, WORDS, MAXO, -1, false>(jobs[j], smem, nkeep, nullptr, t0, t1);
+            }
             __syncthreads();
         }
     }
@@ -815,6 +895,10 @@ DevProps &props(int dev);
 
 int device_cus(int dev) { return props(dev).cus; }
 
+// Static LDS of the MTTKRP kernels (extraction masks, counters) is below
+// this; plans budget it beside their tables and record staging.
+constexpr size_t kStaticLdsAllowance = 2048;
+
 // LDS words staged per nonzero: [value, destination, other coordinates]
 // rounded to 16 bytes.
 int record_words(int nmodes, int words) {
@@ -824,7 +908,7 @@ int record_words(int nmodes, int words) {
 
 size_t tile_plan_lds(const alto_tensor *h, int rank_tile, int slots, int threads) {
     const size_t rec = (size_t)record_words(h->info.nmodes, h->info.index_words);
-    return (size_t)slots * (2 * (rank_tile + 1) + 2) * 4 + (size_t)threads * rec * 4 + 256;
+    return (size_t)slots * (2 * (rank_tile + 1) + 2) * 4 + (size_t)threads * rec * 4 + kStaticLdsAllowance;
 }
 
 bool tile_plan_fits(const alto_tensor *h, int rank_tile, int slots, int threads) {
@@ -844,7 +928,7 @@ alto_status check_launch_lds(const void *kern, size_t dyn, int dev) {
 
 size_t direct_table_limit(const alto_tensor *h, int threads) {
     const size_t rec = (size_t)record_words(h->info.nmodes, h->info.index_words);
-    const size_t stage = (size_t)threads * rec * 4 + 256;              // + static LDS and alignment
+    const size_t stage = (size_t)threads * rec * 4 + kStaticLdsAllowance;  // + static LDS and alignment
     const size_t lds = props(h->device).lds;
     return lds > stage ? lds - stage : 0;
 }
