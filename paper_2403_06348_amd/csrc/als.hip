@@ -18,6 +18,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -165,12 +167,12 @@ __global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict_
 // G = sum of the np partial R x R blocks.  Block b owns entries
 // [64 b, 64 b + 64); its 4 waves take every 4th partial with two independent
 // sums each, then add their results in a fixed order (deterministic).
-__global__ __launch_bounds__(kThreads) void k_gram_reduce(const double *__restrict__ partials, int np, int R,
-                                                          double *__restrict__ G) {
+__device__ inline void gram_reduce_block(const double *__restrict__ partials, int np, int R, double *__restrict__ G,
+                                         int eb) {
     __shared__ double red[4][64];
     const int rr = R * R;
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int e = blockIdx.x * 64 + t;
+    const int e = eb * 64 + t;
     double s0 = 0.0, s1 = 0.0;
     if (e < rr) {
         int p = w;
@@ -185,12 +187,17 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double *__restri
     if (w == 0 && e < rr) G[e] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(const double *__restrict__ partials, int np, int R,
+                                                          double *__restrict__ G) {
+    gram_reduce_block(partials, np, R, G, blockIdx.x);
+}
+
 inline unsigned gram_reduce_blocks(int R) { return (unsigned)((R * R + 63) / 64); }
 
-// Single workgroup.  grams: N x R x R; W: R x R output; flags bit n on fallback.
-__global__ __launch_bounds__(kThreads) void k_als_prepare(const double *__restrict__ grams, int N, int n, int R,
-                                                          double *__restrict__ W, uint32_t *flags) {
-    extern __shared__ double sm[];
+// One workgroup.  grams: N x R x R; W: R x R output; flags bit n on
+// fallback; sm: 3 R x R doubles of LDS.
+__device__ inline void als_prepare(const double *__restrict__ grams, int N, int n, int R, double *__restrict__ W,
+                                   uint32_t *flags, double *sm) {
     double *V = sm;           // R x R
     double *L = sm + R * R;   // R x R (Cholesky factor, then inverse / eigenvectors)
     double *T = L + R * R;    // R x R scratch
@@ -331,10 +338,16 @@ __global__ __launch_bounds__(kThreads) void k_als_prepare(const double *__restri
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_als_prepare(const double *__restrict__ grams, int N, int n, int R,
+                                                          double *__restrict__ W, uint32_t *flags) {
+    extern __shared__ double sm[];
+    als_prepare(grams, N, n, R, W, flags, sm);
+}
+
 // Gn holds the Gram of the updated (unnormalized) factor: lambda = the
 // column norms, then Gn is rescaled in place to the normalized factor's Gram.
-__global__ __launch_bounds__(kThreads) void k_als_finalize(double *__restrict__ Gn, int R, double *__restrict__ lam_ws,
-                                                           double *__restrict__ lam_out) {
+__device__ inline void als_finalize(double *__restrict__ Gn, int R, double *__restrict__ lam_ws,
+                                    double *__restrict__ lam_out) {
     __shared__ double lam[kMaxSweepRank];
     for (int r = threadIdx.x; r < R; r += kThreads) {
         const double l = sqrt(fmax(Gn[r * R + r], 0.0));
@@ -350,17 +363,67 @@ __global__ __launch_bounds__(kThreads) void k_als_finalize(double *__restrict__ 
     }
 }
 
-__global__ void k_als_normalize(float *__restrict__ A, uint64_t I, int R, const double *__restrict__ lam,
-                                uint16_t *__restrict__ shadow) {
+__global__ __launch_bounds__(kThreads) void k_als_finalize(double *__restrict__ Gn, int R, double *__restrict__ lam_ws,
+                                                           double *__restrict__ lam_out) {
+    als_finalize(Gn, R, lam_ws, lam_out);
+}
+
+__device__ inline void als_normalize(float *__restrict__ A, uint64_t I, int R, const double *__restrict__ lam,
+                                     uint16_t *__restrict__ shadow, uint64_t start, uint64_t stride) {
     const uint64_t n = I * R;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    for (uint64_t t = start; t < n; t += stride) {
         const double l = lam[t % R];
         float v = A[t];
         if (l > 0.0) v = (float)((double)v / l);
         A[t] = v;
         if (shadow) shadow[t] = f32_to_bf16_rne(v);
     }
+}
+
+__global__ void k_als_normalize(float *__restrict__ A, uint64_t I, int R, const double *__restrict__ lam,
+                                uint16_t *__restrict__ shadow) {
+    als_normalize(A, I, R, lam, shadow, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                  (uint64_t)gridDim.x * blockDim.x);
+}
+
+// ---- the same R x R steps for many sweeps at once: one launch per step,
+// workgroups indexed by job (blockIdx.x) and, where a job has more work
+// than one workgroup, by part (blockIdx.y)
+struct SweepJob {
+    const double *grams;     // N x R x R Grams
+    double *W;               // R x R solve operator
+    uint32_t *flags;         // pseudo-inverse fallback flags
+    const double *partials;  // P partial R x R Grams
+    double *G;               // Gram the partials are summed into
+    double *lam_ws;          // lambda of the mode (workspace)
+    double *lam_out;         // caller's lambda (last mode) or null
+    float *A;                // factor to normalize
+    uint16_t *shadow;        // its BF16 shadow or null
+    uint64_t I;
+    int N, n, R, P;
+};
+
+__global__ __launch_bounds__(kThreads) void k_als_prepare_b(const SweepJob *__restrict__ jobs) {
+    extern __shared__ double sm[];
+    const SweepJob &j = jobs[blockIdx.x];
+    als_prepare(j.grams, j.N, j.n, j.R, j.W, j.flags, sm);
+}
+
+__global__ __launch_bounds__(kThreads) void k_gram_reduce_b(const SweepJob *__restrict__ jobs) {
+    const SweepJob &j = jobs[blockIdx.x];
+    if ((int)blockIdx.y * 64 >= j.R * j.R) return;  // whole workgroup
+    gram_reduce_block(j.partials, j.P, j.R, j.G, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kThreads) void k_als_finalize_b(const SweepJob *__restrict__ jobs) {
+    const SweepJob &j = jobs[blockIdx.x];
+    als_finalize(j.G, j.R, j.lam_ws, j.lam_out);
+}
+
+__global__ void k_als_normalize_b(const SweepJob *__restrict__ jobs) {
+    const SweepJob &j = jobs[blockIdx.x];
+    als_normalize(j.A, j.I, j.R, j.lam_ws, j.shadow, (uint64_t)blockIdx.y * blockDim.x + threadIdx.x,
+                  (uint64_t)gridDim.y * blockDim.x);
 }
 
 __global__ void k_to_bf16(const float *__restrict__ A, uint64_t n, uint16_t *__restrict__ out) {
@@ -389,9 +452,42 @@ unsigned partial_blocks(uint64_t I) {
     return (unsigned)p;
 }
 
+// Device table of the batched sweep's per-job steps, per (device, stream).
+struct SweepStage {
+    SweepJob *dev = nullptr;
+    size_t cap = 0;
+};
+std::mutex g_sweep_stage_mu;
+std::map<std::pair<int, hipStream_t>, SweepStage> g_sweep_stage;
+
+alto_status upload_sweep_jobs(const std::vector<SweepJob> &host, hipStream_t s, SweepJob **out) {
+    int dev = 0;
+    ALTO_HIP(hipGetDevice(&dev));
+    SweepStage *st;
+    {
+        std::lock_guard<std::mutex> lk(g_sweep_stage_mu);
+        st = &g_sweep_stage[{dev, s}];
+    }
+    if (st->cap < host.size()) {
+        if (st->dev) {
+            ALTO_HIP(hipStreamSynchronize(s));
+            dev_free(st->dev);
+            st->dev = nullptr;
+            st->cap = 0;
+        }
+        if (dev_alloc((void **)&st->dev, host.size() * sizeof(SweepJob)) != hipSuccess)
+            return fail(ALTO_ERR_OOM, "batched sweep staging allocation failed");
+        st->cap = host.size();
+    }
+    ALTO_HIP(hipMemcpyAsync(st->dev, host.data(), host.size() * sizeof(SweepJob), hipMemcpyHostToDevice, s));
+    *out = st->dev;
+    return ALTO_OK;
+}
+
 }  // namespace
 
-alto_status sweep_begin(alto_tensor *h, int rank, int fdt, float *const *factors, const double *lambda,
+// Checks and workspace of one sweep; resets its fallback flags.
+alto_status sweep_setup(alto_tensor *h, int rank, int fdt, float *const *factors, const double *lambda,
                         hipStream_t s) {
     ALTO_CHECK_HANDLE(h);
     const int N = h->info.nmodes;
@@ -420,18 +516,35 @@ alto_status sweep_begin(alto_tensor *h, int rank, int fdt, float *const *factors
             if (st != ALTO_OK) return st;
         }
     }
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, h->ws_flags, (uint64_t)1, 0u);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+// Gram of mode m's factor into partials (and its BF16 shadow).
+void gram_partials(alto_tensor *h, int m, int R, int fdt, float *const *factors, hipStream_t s) {
+    const size_t rr = (size_t)R * R;
+    double *partials = (double *)h->ws_sweep + h->info.nmodes * rr + rr;
+    const uint64_t I = h->info.dims[m];
+    launch_gram_rows<false>(R, partial_blocks(I), s, factors[m], nullptr, nullptr, I, partials);
+    if (fdt == ALTO_BF16)
+        hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(I * R, 256, 16384)), dim3(256), 0, s, factors[m], I * R,
+                           h->ws_bf16[m]);
+}
+
+alto_status sweep_begin(alto_tensor *h, int rank, int fdt, float *const *factors, const double *lambda,
+                        hipStream_t s) {
+    alto_status st = sweep_setup(h, rank, fdt, factors, lambda, s);
+    if (st != ALTO_OK) return st;
+    const int N = h->info.nmodes;
+    const int R = rank;
+    const size_t rr = (size_t)R * R;
     double *grams = (double *)h->ws_sweep;
     double *partials = grams + N * rr + rr;
-    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, h->ws_flags, (uint64_t)1, 0u);
     for (int m = 0; m < N; m++) {
-        const uint64_t I = h->info.dims[m];
-        const unsigned P = partial_blocks(I);
-        launch_gram_rows<false>(R, P, s, factors[m], nullptr, nullptr, I, partials);
-        hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(R)), dim3(kThreads), 0, s, partials, (int)P, R,
-                           grams + m * rr);
-        if (fdt == ALTO_BF16)
-            hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(I * R, 256, 16384)), dim3(256), 0, s, factors[m], I * R,
-                               h->ws_bf16[m]);
+        gram_partials(h, m, R, fdt, factors, s);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(R)), dim3(kThreads), 0, s, partials,
+                           (int)partial_blocks(h->info.dims[m]), R, grams + m * rr);
     }
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
@@ -505,13 +618,64 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *r
     if (count == 0) return ALTO_OK;
     if (!hs || !ranks || !fdts || !factors || !lambdas) return fail(ALTO_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    int maxN = 0;
+    int maxN = 0, maxR = 0;
     for (int j = 0; j < count; j++) {
         if (!factors[j]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(j) + "] is NULL");
-        alto_status st = sweep_begin(hs[j], ranks[j], fdts[j], factors[j], lambdas[j], s);
+        alto_status st = sweep_setup(hs[j], ranks[j], fdts[j], factors[j], lambdas[j], s);
         if (st != ALTO_OK) return fail(st, "item " + std::to_string(j) + ": " + alto_last_error());
         maxN = std::max(maxN, hs[j]->info.nmodes);
+        maxR = std::max(maxR, ranks[j]);
     }
+    // The per-job R x R steps of every mode, in one table uploaded once:
+    // section m holds the jobs that have a mode m, in job order.
+    std::vector<SweepJob> table;
+    std::vector<size_t> sec(maxN + 1, 0);
+    for (int m = 0; m < maxN; m++) {
+        sec[m] = table.size();
+        for (int j = 0; j < count; j++) {
+            alto_tensor *h = hs[j];
+            if (m >= h->info.nmodes) continue;
+            const int R = ranks[j];
+            const size_t rr = (size_t)R * R;
+            double *grams = (double *)h->ws_sweep;
+            double *W = grams + h->info.nmodes * rr;
+            double *partials = W + rr;
+            SweepJob jb;
+            jb.grams = grams;
+            jb.W = W;
+            jb.flags = h->ws_flags;
+            jb.partials = partials;
+            jb.G = grams + m * rr;
+            jb.lam_ws = partials + (size_t)kPartials * rr;
+            jb.lam_out = m == h->info.nmodes - 1 ? lambdas[j] : nullptr;
+            jb.A = factors[j][m];
+            jb.shadow = fdts[j] == ALTO_BF16 ? h->ws_bf16[m] : nullptr;
+            jb.I = h->info.dims[m];
+            jb.N = h->info.nmodes;
+            jb.n = m;
+            jb.R = R;
+            jb.P = (int)partial_blocks(jb.I);
+            table.push_back(jb);
+        }
+    }
+    sec[maxN] = table.size();
+    // normalization workgroups per job: enough for the largest factor
+    uint64_t maxIR = 1;
+    for (const SweepJob &jb : table) maxIR = std::max<uint64_t>(maxIR, jb.I * (uint64_t)jb.R);
+    const unsigned nblk = (unsigned)std::min<uint64_t>(512, (maxIR + 2047) / 2048);
+    SweepJob *dtab = nullptr;
+    alto_status st = upload_sweep_jobs(table, s, &dtab);
+    if (st != ALTO_OK) return st;
+    const unsigned rblocks = gram_reduce_blocks(maxR);
+    // Grams of every factor: the partials of mode m for every job, then one
+    // reduction launch (each job's partial buffer is reused mode by mode)
+    for (int m = 0; m < maxN; m++) {
+        for (int j = 0; j < count; j++)
+            if (m < hs[j]->info.nmodes) gram_partials(hs[j], m, ranks[j], fdts[j], factors[j], s);
+        const unsigned nj = (unsigned)(sec[m + 1] - sec[m]);
+        hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, rblocks), dim3(kThreads), 0, s, dtab + sec[m]);
+    }
+    ALTO_HIP(hipGetLastError());
     std::vector<const void *> fptr((size_t)count * ALTO_MAX_MODES);
     for (int j = 0; j < count; j++) sweep_factor_ptrs(hs[j], fdts[j], factors[j], &fptr[(size_t)j * ALTO_MAX_MODES]);
     // a job that fills the GPU by itself runs its own launch with its mode's
@@ -523,11 +687,13 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *r
     std::vector<const void *const *> bfac;
     std::vector<float *> bout;
     for (int n = 0; n < maxN; n++) {
+        const unsigned nj = (unsigned)(sec[n + 1] - sec[n]);
+        // V, Cholesky and solve operator of mode n for every job
+        hipLaunchKernelGGL(k_als_prepare_b, dim3(nj), dim3(kThreads), (size_t)3 * maxR * maxR * 8, s, dtab + sec[n]);
+        ALTO_HIP(hipGetLastError());
         bh.clear(); bm.clear(); br.clear(); bf.clear(); bfac.clear(); bout.clear();
         for (int j = 0; j < count; j++) {
             if (n >= hs[j]->info.nmodes) continue;
-            alto_status st = sweep_pre(hs[j], n, ranks[j], s);
-            if (st != ALTO_OK) return st;
             if (alone(j)) {
                 alto_mttkrp_plan p;
                 st = resolve_plan(hs[j], n, ranks[j], fdts[j], nullptr, &p);
@@ -545,16 +711,25 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *r
         }
         // the MTTKRPs of mode n of every job in one persistent launch per
         // kernel variant
-        alto_status st = bh.empty() ? ALTO_OK
-                                    : batched_run((int)bh.size(), bh.data(), bm.data(), br.data(), bf.data(),
-                                                  bfac.data(), bout.data(), s);
+        st = bh.empty() ? ALTO_OK
+                        : batched_run((int)bh.size(), bh.data(), bm.data(), br.data(), bf.data(), bfac.data(),
+                                      bout.data(), s);
         if (st != ALTO_OK) return st;
+        // A = M W with the partial Grams of A, per job (the real work), then
+        // the Gram sums, lambda and normalization in one launch each
         for (int j = 0; j < count; j++) {
             if (n >= hs[j]->info.nmodes) continue;
-            st = sweep_post(hs[j], n, ranks[j], fdts[j], factors[j],
-                            n == hs[j]->info.nmodes - 1 ? lambdas[j] : nullptr, s);
-            if (st != ALTO_OK) return st;
+            alto_tensor *h = hs[j];
+            const int R = ranks[j];
+            const size_t rr = (size_t)R * R;
+            double *W = (double *)h->ws_sweep + h->info.nmodes * rr;
+            const uint64_t I = h->info.dims[n];
+            launch_gram_rows<true>(R, partial_blocks(I), s, h->ws_m, W, factors[j][n], I, W + rr);
         }
+        hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, rblocks), dim3(kThreads), 0, s, dtab + sec[n]);
+        hipLaunchKernelGGL(k_als_finalize_b, dim3(nj), dim3(kThreads), 0, s, dtab + sec[n]);
+        hipLaunchKernelGGL(k_als_normalize_b, dim3(nj, nblk), dim3(256), 0, s, dtab + sec[n]);
+        ALTO_HIP(hipGetLastError());
     }
     return ALTO_OK;
 }
