@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs in the serving leg of the default run (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="offered load of the serving runs, as a multiple of a 15 GNNZ/s capacity estimate")
     ap.add_argument("--nnz", type=int, default=None, help="override nonzero count (smaller runs)")
     ap.add_argument("--cpu-sample", type=int, default=40_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -244,12 +246,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.config == "c5":
-        res = serving_run(256, 2e7, 10, 0.7, 64.0, 32)
+        res = serving_run(256, 2e7, 10, args.serve_load, 64.0, 32)
         print(json.dumps({
             "metric": METRIC, "value": res["gnnz_s"], "unit": "GNNZ/s", "n_gpus": 1, "steps": 1, "warmup": 0,
             "ms_per_step": round(res["wall_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "256 CP-ALS jobs, Poisson arrivals at 0.7 x estimated capacity, 3-5 modes, dims "
+            "config": {"workload": f"256 CP-ALS jobs, Poisson arrivals at {args.serve_load} x estimated capacity, 3-5 modes, dims "
                        "log-uniform [1e3,1e6], nnz log-uniform [1e4,2e7], Zipf(1.2), R in {8,16,32}, 10 sweeps "
                        "each, 64 GiB admission budget"},
             "serving": res}), flush=True)
@@ -474,7 +476,7 @@ def main():
         del coords, vals
         torch.cuda.empty_cache()
         alto.release_cached_memory()
-        out["serving"] = serving_run(args.serve_jobs, 2e6, 10, 0.7, 32.0, 16)
+        out["serving"] = serving_run(args.serve_jobs, 2e6, 10, args.serve_load, 32.0, 16)
         out["serving"]["workload"] = ("Poisson stream of 3-5-mode CP-ALS jobs, dims log-uniform [1e3,1e6], nnz "
                                       "log-uniform [1e4,2e6], Zipf(1.2), R in {8,16,32}, 10 sweeps each")
     if not args.no_cpu_baseline:
