@@ -291,16 +291,14 @@ __device__ inline uint64_t compress_lds(uint64_t x, const uint64_t *m) {
     return x;
 }
 
-// Tiles [t0, t1) of one tensor's line, processed by one workgroup.  The LDS
-// table is initialized here and fully flushed by the last tile.
-// TMC: the conflict-resolution mode fixed at compile time (-1: read from the
-// arguments).  FAST: exactly 3 modes, a one-word index, gathers through
-// 32-bit buffer offsets and FP32 atomics into the output, with the
-// extraction masks in LDS (`lmask`) -- the common case, compiled without the
-// branches and the scalar state of the general one.
-template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST>
-__device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep, const uint64_t *lmask,
-                                      uint64_t t0, uint64_t t1) {
+// Tiles [t0, t1) of one tensor's line, processed by one workgroup (the
+// plain, unpipelined loop: single launches of shapes other than the
+// specialised one, and tensors of 6-8 modes in batched launches).  The LDS
+// table is initialized here and fully flushed by the last tile.  TMC: the
+// conflict-resolution mode fixed at compile time (-1: read from the
+// arguments).
+template <int LPN, typename FT, int WORDS, int MAXO, int TMC>
+__device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep, uint64_t t0, uint64_t t1) {
     const int TM = TMC >= 0 ? TMC : a.tile_merge;
     // nonzeros gathered together per group
     constexpr int SB = MAXO == 2 ? (LPN < 4 ? LPN : 4) : (LPN < 2 ? LPN : 2);
@@ -323,7 +321,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
     uint32_t *gst = stage + grp * LPN * REC;
     const int r0 = 4 * q;
     const bool ract = r0 < a.rank;
-    const int nother = FAST ? 2 : a.nmodes - 1;
+    const int nother = a.nmodes - 1;
 
     if (TM) {
         for (int i = tid; i < SK; i += blockDim.x) {
@@ -367,11 +365,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             if (x < gb) {
                 uint32_t c3[3] = {0u, 0u, 0u};
                 uint32_t row;
-                if (FAST) {
-#pragma unroll
-                    for (int m = 0; m < 3; m++) c3[m] = (uint32_t)compress_lds(lo, lmask + 7 * m);
-                    row = a.mode == 0 ? c3[0] : (a.mode == 1 ? c3[1] : c3[2]);
-                } else if (MAXO == 2 && WORDS == 1) {
+                if (MAXO == 2 && WORDS == 1) {
 #pragma unroll
                     for (int m = 0; m < 3; m++)
                         if (m < a.nmodes) c3[m] = extract_mode<1>(a.lp.mode[m], lo, hi);
@@ -445,7 +439,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
 #pragma unroll
                     for (int k = 0; k < MAXO; k++) {
                         if (k < nother) {
-                            if (FAST || a.buf32) {
+                            if (a.buf32) {
                                 const __amdgpu_buffer_rsrc_t rs = factor_rsrc(a.fac_other[k], a.fac_bytes[k]);
 #pragma unroll
                                 for (int s = 0; s < SB; s++) {
@@ -498,7 +492,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
 #pragma unroll
                             for (int j = 0; j < 4; j++) acc[j] += p[s][j];
                         } else {
-                            if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
+                            if (cur != kEmptyRow) flush_run<TMC, false>(a, tval, thits, cur, q, r0, acc);
                             cur = dst;
 #pragma unroll
                             for (int j = 0; j < 4; j++) acc[j] = p[s][j];
@@ -508,9 +502,9 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
             }
             __builtin_amdgcn_wave_barrier();
         }
-        if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
+        if (cur != kEmptyRow) flush_run<TMC, false>(a, tval, thits, cur, q, r0, acc);
 
-        tile_end<FAST>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
+        tile_end<false>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
     }
 }
 
@@ -762,7 +756,7 @@ __global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
         load_masks(a.lp, a.nmodes, lmask);
         mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
     } else {
-        mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
+        mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC>(a, smem, nkeep, t0, t1);
     }
 }
 
@@ -792,7 +786,7 @@ __global__ __launch_bounds__(256, 2) void k_mttkrp_batch(const MttkrpArgs *__res
                 load_masks(jobs[j].lp, jobs[j].nmodes, lmask);
                 mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, -1, false>(jobs[j], smem, nkeep, lmask, t0, t1);
             } else {
-                mttkrp_stretch<LPN, FT, WORDS, MAXO, -1, false>(jobs[j], smem, nkeep, nullptr, t0, t1);
+                mttkrp_stretch<LPN, FT, WORDS, MAXO, -1>(jobs[j], smem, nkeep, t0, t1);
             }
             __syncthreads();
         }
