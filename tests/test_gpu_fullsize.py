@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_cases import rel_fro, say, vals32
+from gpu_cases import bf16_round, rel_fro, say, vals32
 from synth import CONFIGS, make_config, make_factors
 
 pytestmark = pytest.mark.gpu
@@ -68,3 +68,25 @@ def test_full_mttkrp_sampled_rows(name):
         say(f"    {len(rows)} rows: rel err {e:.2e}, worst row {worst:.2e}")
         assert e <= 1e-5
         assert worst <= 1e-4
+
+
+def test_full_c4_bf16_factors_sampled_rows():
+    """Precision form at full size: the c2 tensor with R=64 factors stored as
+    BF16, autotuned plans (rank tiles).  The oracle runs on the same
+    BF16-rounded factors, so the bound is the FP32 accumulation's."""
+    X, T = full("c2")  # the precision form's tensor is the c2 tensor
+    R = CONFIGS["c4"]["rank"]
+    facs = make_factors(X.dims, R, seed=7)
+    gf = [torch.from_numpy(f).cuda().to(torch.bfloat16).view(torch.int16) for f in facs]
+    v64 = vals32(X).astype(np.float64)
+    f64 = [bf16_round(f).astype(np.float64) for f in facs]
+    for n in range(X.nmodes):
+        out = torch.empty((X.dims[n], R), device="cuda")
+        plan = T.autotune(n, gf, out=out, rank=R, fdt=alto.BF16)
+        say(f"[full] c4 mode {n} plan {plan}")
+        got = T.mttkrp(n, gf, out=out, rank=R, fdt=alto.BF16).cpu().numpy().astype(np.float64)
+        rows = sample_rows(X.coords[n], X.dims[n], seed=10 + n)
+        ref = oracle.mttkrp_rows(X.dims, X.coords, v64, f64, n, rows)
+        e = rel_fro(got[rows], ref)
+        say(f"    {len(rows)} rows: rel err {e:.2e}")
+        assert e <= 1e-5
