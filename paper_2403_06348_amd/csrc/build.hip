@@ -85,10 +85,18 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restri
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * TILE;
     const int lane = lane_id();
+    // all of the thread's key loads are issued before the first is used
+    uint32_t dg[RsCfg<WORDS>::IPT];
+#pragma unroll
+    for (int j = 0; j < RsCfg<WORDS>::IPT; j++) {
+        const uint64_t i = base + (uint64_t)j * RS_THREADS + threadIdx.x;
+        dg[j] = i < n ? digit_at<WORDS>(keys + i * WORDS, shift) : 0u;
+    }
+#pragma unroll
     for (int j = 0; j < RsCfg<WORDS>::IPT; j++) {
         const uint64_t i = base + (uint64_t)j * RS_THREADS + threadIdx.x;
         const bool valid = i < n;
-        const uint32_t d = valid ? digit_at<WORDS>(keys + i * WORDS, shift) : 0u;
+        const uint32_t d = dg[j];
         const uint64_t act = __ballot(valid);
         const uint64_t peers = match_byte(d, act);
         // one update per distinct digit of the wave (Zipf inputs repeat keys)
@@ -177,17 +185,20 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__res
     uint64_t kw[IPT][WORDS];
     float kv[IPT];
     uint32_t loc[IPT];
+    // all of the thread's loads are issued before the ranking below uses them
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
         const uint64_t i = tbase + (uint64_t)w * 64 * IPT + (uint64_t)j * 64 + lane;
         const bool valid = i < n;
-        uint32_t d = 0;
-        if (valid) {
 #pragma unroll
-            for (int q = 0; q < WORDS; q++) kw[j][q] = keys_in[i * WORDS + q];
-            kv[j] = vals_in[i];
-            d = digit_at<WORDS>(kw[j], shift);
-        }
+        for (int q = 0; q < WORDS; q++) kw[j][q] = valid ? keys_in[i * WORDS + q] : 0;
+        kv[j] = valid ? vals_in[i] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        const uint64_t i = tbase + (uint64_t)w * 64 * IPT + (uint64_t)j * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t d = valid ? digit_at<WORDS>(kw[j], shift) : 0u;
         const uint64_t act = __ballot(valid);
         const uint64_t peers = match_byte(d, act);
         const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
@@ -246,12 +257,43 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__res
 
 // ------------------------------------------------------------ partition / decode
 
+constexpr int kPartChunk = 8;
+
+// A mode's bits of an index, as a (hi, lo) pair ordered like the coordinate:
+// mask extraction keeps the relative order of the kept bits, so among indices
+// masked to one mode the smallest masked value holds the smallest coordinate
+// (and likewise the largest).  Min and max are therefore taken on masked
+// indices and only the two results are decoded.
+struct PartKey {
+    uint64_t hi, lo;
+};
+
+__device__ inline bool part_less(const PartKey &x, const PartKey &y) {
+    return x.hi < y.hi || (x.hi == y.hi && x.lo < y.lo);
+}
+
+__device__ inline uint64_t shfl_xor64(uint64_t v, int o) {
+    const int a = __shfl_xor((int)(uint32_t)v, o, 64);
+    const int b = __shfl_xor((int)(uint32_t)(v >> 32), o, 64);
+    return (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
+}
+
+template <int WORDS>
+__device__ inline PartKey part_shfl(const PartKey &k, int o) {
+    return PartKey{WORDS == 2 ? shfl_xor64(k.hi, o) : 0, shfl_xor64(k.lo, o)};
+}
+
+// Segments l = 0..nseg-1 (a grid-stride loop of workgroups): start offset and
+// the closed interval of every mode's coordinates.  Per mode, the minimum and
+// maximum masked index are reduced across each wave with shuffles, then across
+// the 4 waves in LDS, and decoded once.
 template <int WORDS>
 __global__ __launch_bounds__(256) void k_partition(const LinePlan lp, const uint64_t *__restrict__ keys, uint64_t n,
                                                    uint64_t nseg, int64_t *__restrict__ starts,
                                                    uint64_t *__restrict__ iv) {
-    __shared__ uint32_t smin[256];
-    __shared__ uint32_t smax[256];
+    __shared__ PartKey wmin[4][ALTO_MAX_MODES], wmax[4][ALTO_MAX_MODES];
+    const int N = lp.nmodes;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
     const uint64_t q = n / nseg, r = n % nseg;
     for (uint64_t l = blockIdx.x; l < nseg; l += gridDim.x) {
         const uint64_t a = l * q + (l * r) / nseg;
@@ -260,38 +302,69 @@ __global__ __launch_bounds__(256) void k_partition(const LinePlan lp, const uint
             starts[l] = (int64_t)a;
             if (l == nseg - 1) starts[nseg] = (int64_t)n;
         }
-#pragma unroll 1
-        for (int m = 0; m < lp.nmodes; m++) {
-            uint32_t mn = 0xFFFFFFFFu, mx = 0;
-            for (uint64_t x = a + threadIdx.x; x < b; x += blockDim.x) {
-                const uint64_t lo = keys[x * WORDS];
-                const uint64_t hi = WORDS == 2 ? keys[x * WORDS + 1] : 0;
-                const uint32_t c = extract_mode<WORDS>(lp.mode[m], lo, hi);
-                mn = min(mn, c);
-                mx = max(mx, c);
-            }
-            smin[threadIdx.x] = mn;
-            smax[threadIdx.x] = mx;
-            __syncthreads();
-            for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-                if ((int)threadIdx.x < s) {
-                    smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + s]);
-                    smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + s]);
-                }
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
-                uint64_t *o = iv + (l * lp.nmodes + m) * 2;
-                if (a == b) {
-                    o[0] = ~uint64_t(0);
-                    o[1] = 0;
-                } else {
-                    o[0] = smin[0];
-                    o[1] = smax[0];
-                }
-            }
-            __syncthreads();
+        PartKey mn[ALTO_MAX_MODES], mx[ALTO_MAX_MODES];
+#pragma unroll
+        for (int m = 0; m < ALTO_MAX_MODES; m++) {
+            mn[m] = PartKey{~uint64_t(0), ~uint64_t(0)};
+            mx[m] = PartKey{0, 0};
         }
+        // chunks of kPartChunk keys per thread, loaded before they are used
+        for (uint64_t x0 = a; x0 < b; x0 += (uint64_t)kPartChunk * blockDim.x) {
+            uint64_t lo[kPartChunk], hi[kPartChunk];
+            bool ok[kPartChunk];
+#pragma unroll
+            for (int j = 0; j < kPartChunk; j++) {
+                const uint64_t x = x0 + (uint64_t)j * blockDim.x + threadIdx.x;
+                ok[j] = x < b;
+                lo[j] = ok[j] ? keys[x * WORDS] : 0;
+                hi[j] = (WORDS == 2 && ok[j]) ? keys[x * WORDS + 1] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kPartChunk; j++) {
+                if (!ok[j]) continue;
+#pragma unroll
+                for (int m = 0; m < ALTO_MAX_MODES; m++) {
+                    if (m < N) {
+                        const PartKey k{WORDS == 2 ? hi[j] & lp.mode[m].w[1].mask : 0, lo[j] & lp.mode[m].w[0].mask};
+                        if (part_less(k, mn[m])) mn[m] = k;
+                        if (part_less(mx[m], k)) mx[m] = k;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < ALTO_MAX_MODES; m++) {
+            if (m < N) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const PartKey u = part_shfl<WORDS>(mn[m], o), v = part_shfl<WORDS>(mx[m], o);
+                    if (part_less(u, mn[m])) mn[m] = u;
+                    if (part_less(mx[m], v)) mx[m] = v;
+                }
+                if (lane == 0) {
+                    wmin[w][m] = mn[m];
+                    wmax[w][m] = mx[m];
+                }
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < N) {
+            const int m = threadIdx.x;
+            PartKey a0 = wmin[0][m], a1 = wmax[0][m];
+            for (int k = 1; k < (int)(blockDim.x >> 6); k++) {
+                if (part_less(wmin[k][m], a0)) a0 = wmin[k][m];
+                if (part_less(a1, wmax[k][m])) a1 = wmax[k][m];
+            }
+            uint64_t *o = iv + (l * N + m) * 2;
+            if (a == b) {  // empty segment: start > end
+                o[0] = ~uint64_t(0);
+                o[1] = 0;
+            } else {
+                o[0] = extract_mode<WORDS>(lp.mode[m], a0.lo, a0.hi);
+                o[1] = extract_mode<WORDS>(lp.mode[m], a1.lo, a1.hi);
+            }
+        }
+        __syncthreads();
     }
 }
 
