@@ -75,6 +75,15 @@ __device__ inline uint32_t digit_at(const uint64_t *k, int shift) {
     return (uint32_t)(w >> (shift & 63)) & 0xFFu;
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin.  Renumbering them so that
+// each XCD takes a contiguous run of tiles puts the blocks whose digit counts
+// and offsets share a cache line (adjacent b of counts[d * nblocks + b]) in
+// the same L2.  The map is a bijection on 0..nblocks-1 whatever the placement.
+__device__ inline uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
+    const uint32_t x = bid & 7u, q = nblocks >> 3, r = nblocks & 7u;
+    return x * q + min(x, r) + (bid >> 3);
+}
+
 // Per-block digit counts, stored digit-major: counts[d * nblocks + b].
 template <int WORDS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restrict__ keys, uint64_t n, int shift,
@@ -83,7 +92,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restri
     __shared__ uint32_t hist[256];
     hist[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * TILE;
+    const uint32_t blk = xcd_tile(blockIdx.x, nblocks);
+    const uint64_t base = (uint64_t)blk * TILE;
     const int lane = lane_id();
     // all of the thread's key loads are issued before the first is used
     uint32_t dg[RsCfg<WORDS>::IPT];
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restri
         if (valid && (peers & ((uint64_t(1) << lane) - 1)) == 0) atomicAdd(&hist[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    counts[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+    counts[(uint64_t)threadIdx.x * nblocks + blk] = hist[threadIdx.x];
 }
 
 constexpr int SC_THREADS = 256;
@@ -181,7 +191,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__res
     for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
     __syncthreads();
 
-    const uint64_t tbase = (uint64_t)blockIdx.x * TILE;
+    const uint32_t blk = xcd_tile(blockIdx.x, nblocks);
+    const uint64_t tbase = (uint64_t)blk * TILE;
     uint64_t kw[IPT][WORDS];
     float kv[IPT];
     uint32_t loc[IPT];
@@ -223,7 +234,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__res
         uint32_t tot;
         const uint32_t ex = block_exclusive_scan<uint32_t>(run, sc, &tot);
         dstart[d] = ex;
-        goff[d] = offsets[(uint64_t)d * nblocks + blockIdx.x];
+        goff[d] = offsets[(uint64_t)d * nblocks + blk];
     }
     __syncthreads();
 #pragma unroll
