@@ -34,6 +34,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPartials = 512;    // partial Gram blocks
 constexpr int kMaxSweepRank = 64;
+constexpr int kMaxPairs = kMaxSweepRank / 2;  // Jacobi rotations per step
 // A job this large runs its MTTKRPs in launches of its own (its mode's plan:
 // whole-mode LDS, rank tiles); smaller ones share the batched launches.
 // Measured on a 256-job serving stream: 2^21 -> 2^23 cut the sweep latency
@@ -263,63 +264,101 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
         }
         return;
     }
-    // ---- fallback: symmetric eigendecomposition by cyclic Jacobi rotations
+    // ---- fallback: symmetric eigendecomposition by parallel cyclic Jacobi.
+    // A step rotates R/2 disjoint index pairs at once (round-robin pairing:
+    // over R-1 steps every pair meets once, a full sweep).  Rotations on
+    // disjoint pairs commute, and each pair's own 2x2 block is touched by its
+    // rotation only, so a step equals applying its rotations one after
+    // another.  R is even (ranks are multiples of 4), so every index is in
+    // exactly one pair and A <- J^T A J splits into independent 2x2 blocks
+    // (pair of the rows, pair of the columns): each block is rotated by its
+    // column pair, then by its row pair, in one pass.
     double *Aj = T;  // working copy
     double *Q = L;
     for (int e = tid; e < R * R; e += kThreads) {
         Aj[e] = V[e];
         Q[e] = (e / R == e % R) ? 1.0 : 0.0;
     }
-    __shared__ double cs[2];
+    __shared__ double rot[kMaxPairs][2];
+    __shared__ int pair[kMaxPairs][2];
+    __shared__ double part[2][kThreads / 64];
     __shared__ double off;
+    const int np = R / 2;
     __syncthreads();
     for (int sweep = 0; sweep < 40; sweep++) {
+        // off-diagonal against diagonal mass, reduced over the workgroup
+        double o = 0.0, d = 0.0;
+        for (int e = tid; e < R * R; e += kThreads) {
+            const double v = Aj[e] * Aj[e];
+            if (e / R == e % R) d += v;
+            else o += v;
+        }
+#pragma unroll
+        for (int w = 32; w > 0; w >>= 1) {
+            o += __shfl_xor(o, w, 64);
+            d += __shfl_xor(d, w, 64);
+        }
+        if ((tid & 63) == 0) {
+            part[0][tid >> 6] = o;
+            part[1][tid >> 6] = d;
+        }
+        __syncthreads();
         if (tid == 0) {
-            double o = 0.0, d = 0.0;
-            for (int p = 0; p < R; p++)
-                for (int q = 0; q < R; q++) {
-                    const double v = Aj[p * R + q] * Aj[p * R + q];
-                    if (p == q) d += v;
-                    else o += v;
-                }
-            off = (o <= 1e-30 * d) ? -1.0 : o;
+            double so = 0.0, sd = 0.0;
+            for (int w = 0; w < kThreads / 64; w++) {
+                so += part[0][w];
+                sd += part[1][w];
+            }
+            off = (so <= 1e-30 * sd) ? -1.0 : so;
         }
         __syncthreads();
         if (off < 0) break;
-        for (int p = 0; p < R - 1; p++) {
-            for (int q = p + 1; q < R; q++) {
-                if (tid == 0) {
-                    const double apq = Aj[p * R + q];
-                    double c = 1.0, s = 0.0;
-                    if (apq != 0.0) {
-                        const double theta = (Aj[q * R + q] - Aj[p * R + p]) / (2.0 * apq);
-                        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                    }
-                    cs[0] = c;
-                    cs[1] = s;
+        for (int step = 0; step < R - 1; step++) {
+            if (tid < np) {
+                int p = tid == 0 ? R - 1 : (step + tid) % (R - 1);
+                int q = tid == 0 ? step : (step - tid + (R - 1)) % (R - 1);
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
                 }
-                __syncthreads();
-                const double c = cs[0], s = cs[1];
-                if (s != 0.0) {
-                    for (int k = tid; k < R; k += kThreads) {  // columns p, q
-                        const double akp = Aj[k * R + p], akq = Aj[k * R + q];
-                        Aj[k * R + p] = c * akp - s * akq;
-                        Aj[k * R + q] = s * akp + c * akq;
-                    }
-                    __syncthreads();
-                    for (int k = tid; k < R; k += kThreads) {  // rows p, q
-                        const double apk = Aj[p * R + k], aqk = Aj[q * R + k];
-                        Aj[p * R + k] = c * apk - s * aqk;
-                        Aj[q * R + k] = s * apk + c * aqk;
-                        const double qkp = Q[k * R + p], qkq = Q[k * R + q];
-                        Q[k * R + p] = c * qkp - s * qkq;
-                        Q[k * R + q] = s * qkp + c * qkq;
-                    }
+                double c = 1.0, sn = 0.0;
+                const double apq = Aj[p * R + q];
+                if (apq != 0.0) {
+                    const double theta = (Aj[q * R + q] - Aj[p * R + p]) / (2.0 * apq);
+                    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                    c = 1.0 / sqrt(t * t + 1.0);
+                    sn = t * c;
                 }
-                __syncthreads();
+                rot[tid][0] = c;
+                rot[tid][1] = sn;
+                pair[tid][0] = p;
+                pair[tid][1] = q;
             }
+            __syncthreads();
+            for (int i = tid; i < np * np; i += kThreads) {  // block (row pair a, column pair b)
+                const int a = i / np, b = i - a * np;
+                const double ca = rot[a][0], sa = rot[a][1], cb = rot[b][0], sb = rot[b][1];
+                if (sa == 0.0 && sb == 0.0) continue;
+                const int p = pair[a][0], q = pair[a][1], u = pair[b][0], v = pair[b][1];
+                const double bpu = Aj[p * R + u], bpv = Aj[p * R + v], bqu = Aj[q * R + u], bqv = Aj[q * R + v];
+                const double xpu = cb * bpu - sb * bpv, xpv = sb * bpu + cb * bpv;
+                const double xqu = cb * bqu - sb * bqv, xqv = sb * bqu + cb * bqv;
+                Aj[p * R + u] = ca * xpu - sa * xqu;
+                Aj[q * R + u] = sa * xpu + ca * xqu;
+                Aj[p * R + v] = ca * xpv - sa * xqv;
+                Aj[q * R + v] = sa * xpv + ca * xqv;
+            }
+            for (int i = tid; i < np * R; i += kThreads) {  // Q <- Q J: columns p, q
+                const int w = i / R, k = i - w * R;
+                const double c = rot[w][0], sn = rot[w][1];
+                if (sn == 0.0) continue;
+                const int p = pair[w][0], q = pair[w][1];
+                const double qkp = Q[k * R + p], qkq = Q[k * R + q];
+                Q[k * R + p] = c * qkp - sn * qkq;
+                Q[k * R + q] = sn * qkp + c * qkq;
+            }
+            __syncthreads();
         }
     }
     __shared__ double emax;

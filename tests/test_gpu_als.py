@@ -105,15 +105,16 @@ def test_sweep_fixed_point_exact_rank():
     T.free()
 
 
-def test_sweep_pseudoinverse_fallback():
-    X = case("c1")
+@pytest.mark.parametrize("name,rank", [("c1", 8), ("c2s", 32), ("c2s", 64)])
+def test_sweep_pseudoinverse_fallback(name, rank):
+    X = case(name)
     coords, vals = upload(X)
     T = alto.AltoTensor(X.dims, coords, vals)
-    facs = factors_for(X, 8, seed=5)
+    facs = factors_for(X, rank, seed=5)
     for n in (1, 2):
         facs[n][:, 3] = facs[n][:, 2]
     gf = [torch.from_numpy(f.copy()).cuda() for f in facs]
-    say("[als] pseudo-inverse fallback")
+    say(f"[als] pseudo-inverse fallback {name} R={rank}")
     T.sweep(gf)
     flags = T.sweep_flags()
     assert flags & 1
