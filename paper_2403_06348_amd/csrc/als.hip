@@ -201,11 +201,17 @@ inline unsigned gram_reduce_blocks(int R) { return (unsigned)((R * R + 63) / 64)
 
 // One workgroup.  grams: N x R x R; W: R x R output; flags bit n on
 // fallback; sm: 3 R x R doubles of LDS.
+// LDS of the solve preparation: three R x R FP64 matrices, row stride R + 1.
+inline size_t prepare_lds_bytes(int R) { return (size_t)3 * R * (R + 1) * sizeof(double); }
+
 __device__ inline void als_prepare(const double *__restrict__ grams, int N, int n, int R, double *__restrict__ W,
                                    uint32_t *flags, double *sm) {
+    // R x R matrices in LDS with row stride R + 1: walks down a column then
+    // touch every bank instead of one
+    const int LD = R + 1;
     double *V = sm;           // R x R
-    double *L = sm + R * R;   // R x R (Cholesky factor, then inverse / eigenvectors)
-    double *T = L + R * R;    // R x R scratch
+    double *L = sm + R * LD;  // R x R (Cholesky factor, then inverse / eigenvectors)
+    double *T = L + R * LD;   // R x R scratch
     __shared__ int not_spd;
     __shared__ double vmax;
     const int tid = threadIdx.x;
@@ -213,14 +219,14 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
         double v = 1.0;
         for (int m = 0; m < N; m++)
             if (m != n) v *= grams[(uint64_t)m * R * R + e];
-        V[e] = v;
-        L[e] = 0.0;
+        V[(e / R) * LD + e % R] = v;
+        L[(e / R) * LD + e % R] = 0.0;
     }
     if (tid == 0) not_spd = 0;
     __syncthreads();
     if (tid == 0) {
         double mx = 0.0;
-        for (int k = 0; k < R; k++) mx = fmax(mx, V[k * R + k]);
+        for (int k = 0; k < R; k++) mx = fmax(mx, V[k * LD + k]);
         vmax = mx;
     }
     __syncthreads();
@@ -228,8 +234,8 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
     // left-looking Cholesky, one column at a time, rows in parallel
     for (int k = 0; k < R; k++) {
         for (int i = k + tid; i < R; i += kThreads) {
-            double t = V[i * R + k];
-            for (int j = 0; j < k; j++) t -= L[i * R + j] * L[k * R + j];
+            double t = V[i * LD + k];
+            for (int j = 0; j < k; j++) t -= L[i * LD + j] * L[k * LD + j];
             T[i] = t;
         }
         __syncthreads();
@@ -240,7 +246,7 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
             break;
         }
         const double lk = sqrt(d);
-        for (int i = k + tid; i < R; i += kThreads) L[i * R + k] = (i == k) ? lk : T[i] / lk;
+        for (int i = k + tid; i < R; i += kThreads) L[i * LD + k] = (i == k) ? lk : T[i] / lk;
         __syncthreads();
     }
     __syncthreads();
@@ -250,8 +256,8 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
         for (int j = tid; j < R; j += kThreads) {
             for (int i = 0; i < R; i++) {
                 double s = (i == j) ? 1.0 : 0.0;
-                for (int k = j; k < i; k++) s -= L[i * R + k] * Li[k * R + j];
-                Li[i * R + j] = (i < j) ? 0.0 : s / L[i * R + i];
+                for (int k = j; k < i; k++) s -= L[i * LD + k] * Li[k * LD + j];
+                Li[i * LD + j] = (i < j) ? 0.0 : s / L[i * LD + i];
             }
         }
         __syncthreads();
@@ -259,7 +265,7 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
         for (int e = tid; e < R * R; e += kThreads) {
             const int r = e / R, s = e % R;
             double w = 0.0;
-            for (int k = (r > s ? r : s); k < R; k++) w += Li[k * R + r] * Li[k * R + s];
+            for (int k = (r > s ? r : s); k < R; k++) w += Li[k * LD + r] * Li[k * LD + s];
             W[e] = w;
         }
         return;
@@ -275,60 +281,61 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
     // column pair, then by its row pair, in one pass.
     double *Aj = T;  // working copy
     double *Q = L;
-    for (int e = tid; e < R * R; e += kThreads) {
+    for (int e = tid; e < R * LD; e += kThreads) {
         Aj[e] = V[e];
-        Q[e] = (e / R == e % R) ? 1.0 : 0.0;
+        Q[e] = (e / LD == e % LD) ? 1.0 : 0.0;
     }
     __shared__ double rot[kMaxPairs][2];
     __shared__ int pair[kMaxPairs][2];
-    __shared__ double part[2][kThreads / 64];
-    __shared__ double off;
+    __shared__ int rotated;
+    __shared__ double fro_part[kThreads / 64];
     const int np = R / 2;
-    __syncthreads();
-    for (int sweep = 0; sweep < 40; sweep++) {
-        // off-diagonal against diagonal mass, reduced over the workgroup
-        double o = 0.0, d = 0.0;
-        for (int e = tid; e < R * R; e += kThreads) {
-            const double v = Aj[e] * Aj[e];
-            if (e / R == e % R) d += v;
-            else o += v;
-        }
+    // threshold Jacobi: a pair is rotated only while its off-diagonal entry
+    // exceeds the FP64 rounding level of V (eps * ||V||_F, the backward error
+    // of a stable eigensolver); a sweep that rotates nothing ends the
+    // iteration.  A relative stopping rule on the off-diagonal mass stalls at
+    // that noise level (rotations among the negligible eigenvalues keep
+    // regenerating it), while the pseudo-inverse drops those eigenvalues.
+    {
+        double f2 = 0.0;
+        for (int e = tid; e < R * R; e += kThreads) f2 += V[(e / R) * LD + e % R] * V[(e / R) * LD + e % R];
 #pragma unroll
-        for (int w = 32; w > 0; w >>= 1) {
-            o += __shfl_xor(o, w, 64);
-            d += __shfl_xor(d, w, 64);
-        }
-        if ((tid & 63) == 0) {
-            part[0][tid >> 6] = o;
-            part[1][tid >> 6] = d;
-        }
+        for (int w = 32; w > 0; w >>= 1) f2 += __shfl_xor(f2, w, 64);
+        if ((tid & 63) == 0) fro_part[tid >> 6] = f2;
+    }
+    __syncthreads();
+    double fro2 = 0.0;
+    for (int w = 0; w < kThreads / 64; w++) fro2 += fro_part[w];
+    const double rot_tol = 2.220446049250313e-16 * sqrt(fro2);
+    for (int sweep = 0; sweep < 40; sweep++) {
+        __syncthreads();  // every thread has read the previous sweep's flag
+        if (tid == 0) rotated = 0;
         __syncthreads();
-        if (tid == 0) {
-            double so = 0.0, sd = 0.0;
-            for (int w = 0; w < kThreads / 64; w++) {
-                so += part[0][w];
-                sd += part[1][w];
-            }
-            off = (so <= 1e-30 * sd) ? -1.0 : so;
-        }
-        __syncthreads();
-        if (off < 0) break;
         for (int step = 0; step < R - 1; step++) {
             if (tid < np) {
-                int p = tid == 0 ? R - 1 : (step + tid) % (R - 1);
-                int q = tid == 0 ? step : (step - tid + (R - 1)) % (R - 1);
+                // round-robin pairing: index R-1 stays, the others rotate;
+                // step + tid < 3R/2 and step - tid + R - 1 < 2R, so one
+                // subtraction reduces each modulo R - 1
+                int p = step + tid, q = step - tid + (R - 1);
+                if (p >= R - 1) p -= R - 1;
+                if (q >= R - 1) q -= R - 1;
+                if (tid == 0) {
+                    p = R - 1;
+                    q = step;
+                }
                 if (p > q) {
                     const int t = p;
                     p = q;
                     q = t;
                 }
                 double c = 1.0, sn = 0.0;
-                const double apq = Aj[p * R + q];
-                if (apq != 0.0) {
-                    const double theta = (Aj[q * R + q] - Aj[p * R + p]) / (2.0 * apq);
+                const double apq = Aj[p * LD + q];
+                if (fabs(apq) > rot_tol) {
+                    const double theta = (Aj[q * LD + q] - Aj[p * LD + p]) / (2.0 * apq);
                     const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
                     c = 1.0 / sqrt(t * t + 1.0);
                     sn = t * c;
+                    atomicOr(&rotated, 1);
                 }
                 rot[tid][0] = c;
                 rot[tid][1] = sn;
@@ -336,35 +343,38 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
                 pair[tid][1] = q;
             }
             __syncthreads();
-            for (int i = tid; i < np * np; i += kThreads) {  // block (row pair a, column pair b)
-                const int a = i / np, b = i - a * np;
+            // blocks (row pair a, column pair b): 32 x 8 threads tile the
+            // np x np blocks, no index division
+            for (int a = tid >> 3; a < np; a += kThreads / 8)
+            for (int b = tid & 7; b < np; b += 8) {
                 const double ca = rot[a][0], sa = rot[a][1], cb = rot[b][0], sb = rot[b][1];
                 if (sa == 0.0 && sb == 0.0) continue;
                 const int p = pair[a][0], q = pair[a][1], u = pair[b][0], v = pair[b][1];
-                const double bpu = Aj[p * R + u], bpv = Aj[p * R + v], bqu = Aj[q * R + u], bqv = Aj[q * R + v];
+                const double bpu = Aj[p * LD + u], bpv = Aj[p * LD + v], bqu = Aj[q * LD + u], bqv = Aj[q * LD + v];
                 const double xpu = cb * bpu - sb * bpv, xpv = sb * bpu + cb * bpv;
                 const double xqu = cb * bqu - sb * bqv, xqv = sb * bqu + cb * bqv;
-                Aj[p * R + u] = ca * xpu - sa * xqu;
-                Aj[q * R + u] = sa * xpu + ca * xqu;
-                Aj[p * R + v] = ca * xpv - sa * xqv;
-                Aj[q * R + v] = sa * xpv + ca * xqv;
+                Aj[p * LD + u] = ca * xpu - sa * xqu;
+                Aj[q * LD + u] = sa * xpu + ca * xqu;
+                Aj[p * LD + v] = ca * xpv - sa * xqv;
+                Aj[q * LD + v] = sa * xpv + ca * xqv;
             }
-            for (int i = tid; i < np * R; i += kThreads) {  // Q <- Q J: columns p, q
-                const int w = i / R, k = i - w * R;
+            for (int w = tid >> 6; w < np; w += kThreads / 64)  // Q <- Q J: columns p, q
+            for (int k = tid & 63; k < R; k += 64) {
                 const double c = rot[w][0], sn = rot[w][1];
                 if (sn == 0.0) continue;
                 const int p = pair[w][0], q = pair[w][1];
-                const double qkp = Q[k * R + p], qkq = Q[k * R + q];
-                Q[k * R + p] = c * qkp - sn * qkq;
-                Q[k * R + q] = sn * qkp + c * qkq;
+                const double qkp = Q[k * LD + p], qkq = Q[k * LD + q];
+                Q[k * LD + p] = c * qkp - sn * qkq;
+                Q[k * LD + q] = sn * qkp + c * qkq;
             }
             __syncthreads();
         }
+        if (rotated == 0) break;  // uniform: read after the step's barrier
     }
     __shared__ double emax;
     if (tid == 0) {
         double mx = 0.0;
-        for (int k = 0; k < R; k++) mx = fmax(mx, fabs(Aj[k * R + k]));
+        for (int k = 0; k < R; k++) mx = fmax(mx, fabs(Aj[k * LD + k]));
         emax = mx;
         atomicOr(flags, 1u << n);
     }
@@ -374,8 +384,8 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
         const int r = e / R, s = e % R;
         double w = 0.0;
         for (int k = 0; k < R; k++) {
-            const double lam = Aj[k * R + k];
-            if (lam > cut) w += Q[r * R + k] * Q[s * R + k] / lam;
+            const double lam = Aj[k * LD + k];
+            if (lam > cut) w += Q[r * LD + k] * Q[s * LD + k] / lam;
         }
         W[e] = w;
     }
@@ -602,7 +612,7 @@ alto_status sweep_pre(alto_tensor *h, int n, int rank, hipStream_t s) {
     const size_t rr = (size_t)rank * rank;
     double *grams = (double *)h->ws_sweep;
     double *W = grams + h->info.nmodes * rr;
-    hipLaunchKernelGGL(k_als_prepare, dim3(1), dim3(kThreads), 3 * rr * 8, s, grams, h->info.nmodes, n, rank, W,
+    hipLaunchKernelGGL(k_als_prepare, dim3(1), dim3(kThreads), prepare_lds_bytes(rank), s, grams, h->info.nmodes, n, rank, W,
                        h->ws_flags);
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
@@ -732,7 +742,7 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *r
     for (int n = 0; n < maxN; n++) {
         const unsigned nj = (unsigned)(sec[n + 1] - sec[n]);
         // V, Cholesky and solve operator of mode n for every job
-        hipLaunchKernelGGL(k_als_prepare_b, dim3(nj), dim3(kThreads), (size_t)3 * maxR * maxR * 8, s, dtab + sec[n]);
+        hipLaunchKernelGGL(k_als_prepare_b, dim3(nj), dim3(kThreads), prepare_lds_bytes(maxR), s, dtab + sec[n]);
         ALTO_HIP(hipGetLastError());
         bh.clear(); bm.clear(); br.clear(); bf.clear(); bfac.clear(); bout.clear();
         for (int j = 0; j < count; j++) {
