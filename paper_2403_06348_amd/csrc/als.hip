@@ -91,7 +91,59 @@ __global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict_
             *(float4 *)(sa + row * STR + 4 * q) = s4[v];
         }
         __syncthreads();
-        if (APPLY && tid < rows) {
+        if (APPLY && RB >= 32) {
+            // register tiles of A = M W: thread (rg, cg) computes rows
+            // 4 rg .. 4 rg + 3 and columns cg*CG .. +CG-1, so each W value
+            // read from LDS serves four rows
+            constexpr int CG = RB / 4;
+            const int cg = tid & 3, rg = tid >> 2;
+            double o[4][CG];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < CG; j++) o[i][j] = 0.0;
+            if (4 * rg < rows) {
+                for (int k0 = 0; k0 < R; k0 += 4) {
+                    float4 m4[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) m4[i] = *(const float4 *)(sa + (4 * rg + i) * STR + k0);
+#pragma unroll
+                    for (int kk = 0; kk < 4; kk++) {
+                        const double *wk = sw + (k0 + kk) * RB + cg * CG;
+                        double mk[4];
+#pragma unroll
+                        for (int i = 0; i < 4; i++)
+                            mk[i] = (double)(kk == 0 ? m4[i].x : kk == 1 ? m4[i].y : kk == 2 ? m4[i].z : m4[i].w);
+#pragma unroll
+                        for (int j = 0; j < CG; j += 2) {
+                            const double2 w2 = *(const double2 *)(wk + j);
+#pragma unroll
+                            for (int i = 0; i < 4; i++) {
+                                o[i][j] = fma(mk[i], w2.x, o[i][j]);
+                                o[i][j + 1] = fma(mk[i], w2.y, o[i][j + 1]);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // every tile has read its rows of M from sa
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int row = 4 * rg + i;
+                if (row >= rows) break;
+                float4 *dst = (float4 *)(A + (c + row) * R);
+#pragma unroll
+                for (int j = 0; j < CG; j += 4) {
+                    const int col = cg * CG + j;
+                    if (col < R) {
+                        const float4 f = make_float4((float)o[i][j], (float)o[i][j + 1], (float)o[i][j + 2],
+                                                     (float)o[i][j + 3]);
+                        dst[col / 4] = f;
+                        *(float4 *)(sa + row * STR + col) = f;
+                    }
+                }
+            }
+        } else if (APPLY && tid < rows) {
             float m[RB];
 #pragma unroll
             for (int k = 0; k < RB; k += 4) {
