@@ -35,6 +35,7 @@ constexpr int kThreads = 256;
 constexpr int kPartials = 512;    // partial Gram blocks
 constexpr int kMaxSweepRank = 64;
 constexpr int kMaxPairs = kMaxSweepRank / 2;  // Jacobi rotations per step
+static_assert(kThreads == 8 * kMaxPairs && kMaxSweepRank <= 64, "Jacobi step thread layout: 32 x 8 blocks, 4 x 64 Q rows");
 // A job this large runs its MTTKRPs in launches of its own (its mode's plan:
 // whole-mode LDS, rank tiles); smaller ones share the batched launches.
 // Measured on a 256-job serving stream: 2^21 -> 2^23 cut the sweep latency
@@ -287,6 +288,7 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
     for (int k = 0; k < R; k++) {
         for (int i = k + tid; i < R; i += kThreads) {
             double t = V[i * LD + k];
+#pragma unroll 4
             for (int j = 0; j < k; j++) t -= L[i * LD + j] * L[k * LD + j];
             T[i] = t;
         }
@@ -308,6 +310,7 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
         for (int j = tid; j < R; j += kThreads) {
             for (int i = 0; i < R; i++) {
                 double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll 4
                 for (int k = j; k < i; k++) s -= L[i * LD + k] * Li[k * LD + j];
                 Li[i * LD + j] = (i < j) ? 0.0 : s / L[i * LD + i];
             }
@@ -317,6 +320,7 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
         for (int e = tid; e < R * R; e += kThreads) {
             const int r = e / R, s = e % R;
             double w = 0.0;
+#pragma unroll 4
             for (int k = (r > s ? r : s); k < R; k++) w += Li[k * LD + r] * Li[k * LD + s];
             W[e] = w;
         }
@@ -395,29 +399,70 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
                 pair[tid][1] = q;
             }
             __syncthreads();
-            // blocks (row pair a, column pair b): 32 x 8 threads tile the
-            // np x np blocks, no index division
-            for (int a = tid >> 3; a < np; a += kThreads / 8)
-            for (int b = tid & 7; b < np; b += 8) {
-                const double ca = rot[a][0], sa = rot[a][1], cb = rot[b][0], sb = rot[b][1];
-                if (sa == 0.0 && sb == 0.0) continue;
-                const int p = pair[a][0], q = pair[a][1], u = pair[b][0], v = pair[b][1];
-                const double bpu = Aj[p * LD + u], bpv = Aj[p * LD + v], bqu = Aj[q * LD + u], bqv = Aj[q * LD + v];
-                const double xpu = cb * bpu - sb * bpv, xpv = sb * bpu + cb * bpv;
-                const double xqu = cb * bqu - sb * bqv, xqv = sb * bqu + cb * bqv;
-                Aj[p * LD + u] = ca * xpu - sa * xqu;
-                Aj[q * LD + u] = sa * xpu + ca * xqu;
-                Aj[p * LD + v] = ca * xpv - sa * xqv;
-                Aj[q * LD + v] = sa * xpv + ca * xqv;
-            }
-            for (int w = tid >> 6; w < np; w += kThreads / 64)  // Q <- Q J: columns p, q
-            for (int k = tid & 63; k < R; k += 64) {
-                const double c = rot[w][0], sn = rot[w][1];
-                if (sn == 0.0) continue;
-                const int p = pair[w][0], q = pair[w][1];
-                const double qkp = Q[k * LD + p], qkq = Q[k * LD + q];
-                Q[k * LD + p] = c * qkp - sn * qkq;
-                Q[k * LD + q] = sn * qkp + c * qkq;
+            // blocks (row pair a, column pair b): thread (a, b0) of a 32 x 8
+            // grid takes column pairs b0, b0 + 8, b0 + 16, b0 + 24 (R <= 64), and
+            // Q's rows k = tid mod 64 for pairs w0, w0 + 4, ..., w0 + 28.  Each
+            // thread issues all of its loads before its stores; the blocks and
+            // Q entries of different threads and pairs are disjoint.
+            {
+                constexpr int NB = kMaxPairs / 8, NQ = kMaxPairs / 4;
+                const int a = tid >> 3, b0 = tid & 7;
+                if (a < np) {
+                    const double ca = rot[a][0], sa = rot[a][1];
+                    const int p = pair[a][0], q = pair[a][1];
+                    double blk[NB][4], cb[NB], sb[NB];
+                    int u[NB], v[NB];
+#pragma unroll
+                    for (int j = 0; j < NB; j++) {
+                        const int bb = b0 + 8 * j;
+                        cb[j] = 1.0;
+                        sb[j] = 0.0;
+                        u[j] = v[j] = 0;
+                        if (bb < np) {
+                            cb[j] = rot[bb][0];
+                            sb[j] = rot[bb][1];
+                            u[j] = pair[bb][0];
+                            v[j] = pair[bb][1];
+                            blk[j][0] = Aj[p * LD + u[j]];
+                            blk[j][1] = Aj[p * LD + v[j]];
+                            blk[j][2] = Aj[q * LD + u[j]];
+                            blk[j][3] = Aj[q * LD + v[j]];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < NB; j++) {
+                        if (b0 + 8 * j >= np || (sa == 0.0 && sb[j] == 0.0)) continue;
+                        const double xpu = cb[j] * blk[j][0] - sb[j] * blk[j][1];
+                        const double xpv = sb[j] * blk[j][0] + cb[j] * blk[j][1];
+                        const double xqu = cb[j] * blk[j][2] - sb[j] * blk[j][3];
+                        const double xqv = sb[j] * blk[j][2] + cb[j] * blk[j][3];
+                        Aj[p * LD + u[j]] = ca * xpu - sa * xqu;
+                        Aj[q * LD + u[j]] = sa * xpu + ca * xqu;
+                        Aj[p * LD + v[j]] = ca * xpv - sa * xqv;
+                        Aj[q * LD + v[j]] = sa * xpv + ca * xqv;
+                    }
+                }
+                const int w0 = tid >> 6, k = tid & 63;
+                if (k < R) {
+                    double qp[NQ], qq[NQ];
+#pragma unroll
+                    for (int j = 0; j < NQ; j++) {
+                        const int w = w0 + 4 * j;
+                        if (w < np) {
+                            qp[j] = Q[k * LD + pair[w][0]];
+                            qq[j] = Q[k * LD + pair[w][1]];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < NQ; j++) {
+                        const int w = w0 + 4 * j;
+                        if (w >= np) continue;
+                        const double c = rot[w][0], sn = rot[w][1];
+                        if (sn == 0.0) continue;
+                        Q[k * LD + pair[w][0]] = c * qp[j] - sn * qq[j];
+                        Q[k * LD + pair[w][1]] = sn * qp[j] + c * qq[j];
+                    }
+                }
             }
             __syncthreads();
         }
@@ -432,13 +477,17 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
     }
     __syncthreads();
     const double cut = (double)R * 2.220446049250313e-16 * emax;
+    __shared__ double ilam[kMaxSweepRank];  // 1/lambda_k, 0 for dropped eigenvalues
+    for (int k = tid; k < R; k += kThreads) {
+        const double lam = Aj[k * LD + k];
+        ilam[k] = lam > cut ? 1.0 / lam : 0.0;
+    }
+    __syncthreads();
     for (int e = tid; e < R * R; e += kThreads) {
         const int r = e / R, s = e % R;
         double w = 0.0;
-        for (int k = 0; k < R; k++) {
-            const double lam = Aj[k * LD + k];
-            if (lam > cut) w += Q[r * LD + k] * Q[s * LD + k] / lam;
-        }
+#pragma unroll 4
+        for (int k = 0; k < R; k++) w += Q[r * LD + k] * Q[s * LD + k] * ilam[k];
         W[e] = w;
     }
 }
