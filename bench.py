@@ -15,7 +15,11 @@ whole steps (2 x nmodes MTTKRPs per step, format generation included).
 (index + value + the (N-1) gathered factor rows per nonzero, plus the output
 once) over its HIP-event-timed launch duration, against 8 TB/s HBM.
 `cpu_baseline` is the FP64 oracle (plain single-threaded C loop) timed on a
-bounded sample of the same tensor on this machine's host.
+bounded sample of the same tensor on this machine's host; `cpu_parallel` is
+the paper's best COO configuration on CPUs (OpenMP over nonzeros, private
+per-thread outputs) on all of the tensor and the host's OpenMP threads.
+`serving` runs the 256-job CP-ALS stream (nnz up to 2e7) through the
+continuous-batching server under an HBM admission budget that binds.
 """
 
 from __future__ import annotations
@@ -34,7 +38,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "MTTKRP GNNZ/s + % HBM roofline (R=16); served CP-ALS sweep p50/p99"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mttkrp_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2403_06348_amd", "csrc", "mttkrp.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2403_06348_amd", "csrc", "mttkrp_kernels.h")
 
 
 def log(*a):
@@ -68,7 +72,21 @@ def traffic_for(workload: str):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(X, rank, budget_nnz):
+    """The single-threaded FP64 oracle on the first `budget_nnz` nonzeros (a
+    uniform sample: the generator draws nonzeros independently), MTTKRP on
+    every mode, median of 3 runs."""
     import numpy as np
 
     import oracle
@@ -78,17 +96,52 @@ def cpu_baseline(X, rank, budget_nnz):
     coords = np.ascontiguousarray(X.coords[:, :m])
     vals = X.vals[:m].astype(np.float64)
     facs = [f.astype(np.float64) for f in make_factors(X.dims, rank, seed=7)]
-    t0 = time.perf_counter()
-    for n in range(X.nmodes):
-        oracle.mttkrp(X.dims, coords, vals, facs, n)
-    dt = time.perf_counter() - t0
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        for n in range(X.nmodes):
+            oracle.mttkrp(X.dims, coords, vals, facs, n)
+        runs.append(time.perf_counter() - t0)
+    dt = float(np.median(runs))
     return {
         "value": round(m * X.nmodes / dt / 1e9, 6),
         "unit": "GNNZ/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"first {m} of {X.nnz} nonzeros (generator order, a uniform sample), MTTKRP on all "
-        f"{X.nmodes} modes, FP64 single-threaded C loop, {dt:.1f} s",
+        f"{X.nmodes} modes, FP64 single-threaded C loop, median of 3 runs of {dt:.2f} s",
+        "nproc": os.cpu_count(),
+        "cpu_model": cpu_model(),
+    }
+
+
+def cpu_parallel(X, rank):
+    """The parallel CPU baseline: OpenMP over the COO nonzeros with private
+    per-thread outputs (the paper's best COO configuration), FP64, the whole
+    tensor, MTTKRP on every mode, median of 3 runs."""
+    import numpy as np
+
+    import oracle
+    from synth import make_factors
+
+    vals = X.vals.astype(np.float64)
+    facs = [f.astype(np.float64) for f in make_factors(X.dims, rank, seed=7)]
+    runs, used = [], 0
+    for _ in range(3):
+        t0 = time.perf_counter()
+        for n in range(X.nmodes):
+            _, used = oracle.mttkrp_parallel(X.dims, X.coords, vals, facs, n)
+        runs.append(time.perf_counter() - t0)
+    dt = float(np.median(runs))
+    return {
+        "value": round(X.nnz * X.nmodes / dt / 1e9, 6),
+        "unit": "GNNZ/s",
+        "cores": used,
+        "kind": "openmp-coo",
+        "sample": f"all {X.nnz} nonzeros, MTTKRP on all {X.nmodes} modes, FP64, OpenMP over nonzeros with "
+        f"per-thread private outputs, {used} threads, median of 3 runs of {dt:.2f} s",
+        "nproc": os.cpu_count(),
+        "cpu_model": cpu_model(),
     }
 
 
@@ -161,6 +214,60 @@ def traffic_from(pmc_dirs, workload, nmodes):
     print(json.dumps(out))
 
 
+def phi_leg(T, X, facs, rank, words, ev):
+    """CP-APR model update Phi on the bench tensor, every mode: ALTO-OTF (Pi
+    rows formed on the fly), the Pi precompute, and ALTO-PRE (Pi rows read).
+    Median of 10 calls each, HIP events on the launch stream.  Byte models
+    (every per-nonzero row access counted, as for MTTKRP): OTF reads index,
+    value, the N-1 factor rows and B's row per nonzero; PRE reads index,
+    value, the Pi row and B's row; the precompute reads index and N-1 rows
+    and writes the Pi row; each Phi writes its output once."""
+    import numpy as np
+    import torch
+
+    N = X.nmodes
+    res = {"rank": rank, "eps": 1e-10, "modes": []}
+    for n in range(N):
+        B = torch.rand((X.dims[n], rank), generator=torch.Generator(device="cuda").manual_seed(n), device="cuda")
+        B.mul_(0.9).add_(0.1)
+        out = torch.empty((X.dims[n], rank), device="cuda")
+
+        def med(fn):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(10):
+                ev[0].record()
+                fn()
+                ev[1].record()
+                torch.cuda.synchronize()
+                ts.append(ev[0].elapsed_time(ev[1]))
+            return float(np.median(ts))
+
+        otf_ms = med(lambda: T.cpapr_phi(n, facs, B, eps=1e-10, out=out))
+        pi = torch.empty((X.nnz, rank), device="cuda")
+        pi_ms = med(lambda: T.cpapr_pi(n, facs, out=pi))
+        pre_ms = med(lambda: T.cpapr_phi(n, None, B, eps=1e-10, pi=pi, out=out))
+        del pi
+        torch.cuda.empty_cache()
+        row = rank * 4
+        b_otf = X.nnz * (8 * words + 4 + (N - 1) * row + row) + X.dims[n] * row
+        b_pre = X.nnz * (8 * words + 4 + row + row) + X.dims[n] * row
+        b_pi = X.nnz * (8 * words + (N - 1) * row + row)
+        res["modes"].append({
+            "mode": n, "otf_ms": round(otf_ms, 4), "pre_ms": round(pre_ms, 4), "pi_ms": round(pi_ms, 4),
+            "otf_gbs": round(b_otf / otf_ms / 1e6, 1), "pre_gbs": round(b_pre / pre_ms / 1e6, 1),
+            "pi_gbs": round(b_pi / pi_ms / 1e6, 1),
+            "otf_frac": round(b_otf / otf_ms / 1e6 / HBM_PEAK_GBS, 4),
+            "pre_frac": round(b_pre / pre_ms / 1e6 / HBM_PEAK_GBS, 4),
+            "alg_bytes": {"otf": b_otf, "pre": b_pre, "pi": b_pi},
+        })
+        log(f"[bench] phi mode {n}: OTF {otf_ms:.3f} ms, Pi {pi_ms:.3f} ms, PRE {pre_ms:.3f} ms")
+    tot_otf = sum(m["otf_ms"] for m in res["modes"])
+    res["otf_gnnz_s"] = round(X.nnz * N / (tot_otf * 1e-3) / 1e9, 3)
+    return res
+
+
 def serving_run(njobs, nnz_hi, sweeps, load, budget_gb, max_active, seed=5):
     """The continuous-batching server on a Poisson stream of CP-ALS jobs.
     Returns a dict with sweep-latency percentiles and aggregate throughput."""
@@ -214,11 +321,15 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
-    ap.add_argument("--serve-jobs", type=int, default=48, help="jobs in the serving leg of the default run (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=256, help="jobs in the serving leg of the default run (0: skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0,
+                    help="HBM admission budget of the serving runs (small enough that admission binds)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load of the serving runs, as a multiple of a 15 GNNZ/s capacity estimate")
     ap.add_argument("--nnz", type=int, default=None, help="override nonzero count (smaller runs)")
-    ap.add_argument("--cpu-sample", type=int, default=40_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=10_000_000)
+    ap.add_argument("--no-cpu-parallel", action="store_true")
+    ap.add_argument("--no-phi", action="store_true", help="skip the CP-APR Phi leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default=None, help="JSON MTTKRP plan override")
     ap.add_argument("--no-autotune", action="store_true")
@@ -246,14 +357,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.config == "c5":
-        res = serving_run(256, 2e7, 10, args.serve_load, 64.0, 32)
+        res = serving_run(256, 2e7, 10, args.serve_load, args.serve_budget_gb, 32)
         print(json.dumps({
             "metric": METRIC, "value": res["gnnz_s"], "unit": "GNNZ/s", "n_gpus": 1, "steps": 1, "warmup": 0,
             "ms_per_step": round(res["wall_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"256 CP-ALS jobs, Poisson arrivals at {args.serve_load} x estimated capacity, 3-5 modes, dims "
                        "log-uniform [1e3,1e6], nnz log-uniform [1e4,2e7], Zipf(1.2), R in {8,16,32}, 10 sweeps "
-                       "each, 64 GiB admission budget"},
+                       f"each, {args.serve_budget_gb:g} GiB admission budget"},
             "serving": res}), flush=True)
         return
     spec = CONFIGS[args.config]
@@ -403,6 +514,7 @@ def main():
             of = outs[n].double()
             bf16_err.append(float((ob - of).norm() / of.norm()))
             del ob, of
+    phi = None if args.no_phi else phi_leg(T, X, facs0, rank, info_words, ev)
     T.free()
     torch.cuda.synchronize()
     tb = time.perf_counter()
@@ -471,17 +583,22 @@ def main():
             "sweeps_per_step": nsweeps,
             "plans": plans,
         },
+        "cpapr_phi": phi,
     }
     if args.serve_jobs > 0:
         del coords, vals
         torch.cuda.empty_cache()
         alto.release_cached_memory()
-        out["serving"] = serving_run(args.serve_jobs, 2e6, 10, args.serve_load, 32.0, 16)
-        out["serving"]["workload"] = ("Poisson stream of 3-5-mode CP-ALS jobs, dims log-uniform [1e3,1e6], nnz "
-                                      "log-uniform [1e4,2e6], Zipf(1.2), R in {8,16,32}, 10 sweeps each")
+        out["serving"] = serving_run(args.serve_jobs, 2e7, 10, args.serve_load, args.serve_budget_gb, 32)
+        out["serving"]["workload"] = (f"{args.serve_jobs} CP-ALS jobs with Poisson arrivals, 3-5 modes, dims "
+                                      "log-uniform [1e3,1e6], nnz log-uniform [1e4,2e7], Zipf(1.2), R in {8,16,32}, "
+                                      f"10 sweeps each, {args.serve_budget_gb:g} GiB admission budget, 32 slots")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(X, rank, args.cpu_sample)
+        if not args.no_cpu_parallel:
+            log("[bench] timing the parallel CPU baseline")
+            out["cpu_parallel"] = cpu_parallel(X, rank)
     print(json.dumps(out), flush=True)
 
 

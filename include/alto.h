@@ -68,8 +68,20 @@ typedef enum { ALTO_F32 = 0, ALTO_BF16 = 1 } alto_dtype;
  *   of it) is held in LDS for the workgroup's whole line segment and added to
  *   the output once at its end (the paper's temporary rows indexed by the mode
  *   interval, which then spans the whole mode).
+ * ALTO_CR_HOT: each workgroup picks the rows its line segment updates most
+ *   often (from a strided sample of the segment) and merges their updates in
+ *   LDS for the whole segment, adding each to the output once at its end;
+ *   updates of all other rows merge in registers and go to the output
+ *   directly.  The paper's temporary rows restricted to the segment's
+ *   high-reuse rows (tensors of up to 5 modes).
  * ALTO_CR_AUTO: chosen per mode from the fiber reuse nnz / dims[mode]. */
-typedef enum { ALTO_CR_AUTO = 0, ALTO_CR_TILE = 1, ALTO_CR_RUN = 2, ALTO_CR_DIRECT = 3 } alto_conflict;
+typedef enum {
+    ALTO_CR_AUTO = 0,
+    ALTO_CR_TILE = 1,
+    ALTO_CR_RUN = 2,
+    ALTO_CR_DIRECT = 3,
+    ALTO_CR_HOT = 4
+} alto_conflict;
 
 /* Where the merged output rows are summed.
  * ALTO_ACC_F64: in an FP64 buffer (handle workspace), rounded once to FP32.
@@ -91,7 +103,7 @@ typedef struct {
     int conflict;        /* alto_conflict                                          */
     int tile_nnz;        /* nonzeros per workgroup tile (line segment length)      */
     int block_threads;   /* 256, 512 or 1024                                       */
-    int table_slots;     /* LDS merge-table rows (power of two), TILE only         */
+    int table_slots;     /* LDS merge-table rows (power of two), TILE and HOT      */
     int accumulate;      /* alto_accumulate                                        */
     int rank_tile;       /* columns per pass (multiple of 4 dividing rank; 0: all) */
 } alto_mttkrp_plan;
@@ -219,6 +231,36 @@ alto_status alto_mttkrp_batched(int count, const alto_handle *hs /*host*/, const
                                 const void *const *const *factors /*host[count] of host[nmodes]*/,
                                 float *const *outs /*host[count]*/, void *stream);
 
+/* ---------------------------------------------------------------- CP-APR */
+
+/*
+ * CP-APR model update of mode `mode` (Algorithm "alg:cp-apr-mu", the Phi
+ * line; Algorithm "fig:subproblem_algo"):
+ *   Phi(i, :) = sum over nonzeros x with i_mode(x) = i of
+ *               val(x) / max(B(i, :) . krp_x, eps) * krp_x,
+ * krp_x = Hadamard product of the other factors' rows A^(m)(i_m(x), :) --
+ * the rows of the Khatri-Rao product Pi that the nonzeros need.
+ * pi == NULL: krp is formed on the fly from `factors` (ALTO-OTF: factors[m]
+ * device FP32 dims[m] x rank for m != mode).  Otherwise pi (device FP32,
+ * nnz x rank, row x = krp of the x-th nonzero of the ordered line, from
+ * alto_cpapr_pi) is read instead (ALTO-PRE; factors may be NULL; needs
+ * nnz < 2^32).  B: device FP32 dims[mode] x rank; phi: device FP32
+ * dims[mode] x rank, overwritten.  eps > 0.  rank: multiple of 4 in 4..128,
+ * whole rank in one pass (the dot product needs every column); tensors of up
+ * to 5 modes.  plan: as for alto_mttkrp_ex (NULL = the mode's MTTKRP plan,
+ * adapted: no rank tiles, tables shrunk to fit).
+ */
+alto_status alto_cpapr_phi(alto_handle h, int mode, int rank, const float *const *factors, const float *B, float eps,
+                           const float *pi, float *phi, const alto_mttkrp_plan *plan, void *stream);
+
+/*
+ * Pi for mode `mode` restricted to the nonzeros (Algorithm "alg:cp-apr-mu",
+ * Pi line), for ALTO-PRE: pi (device FP32, nnz x rank, caller-owned;
+ * nnz * rank * 4 bytes) row x = Hadamard product of the other factors' rows
+ * at the x-th nonzero of the ordered line.
+ */
+alto_status alto_cpapr_pi(alto_handle h, int mode, int rank, const float *const *factors, float *pi, void *stream);
+
 /* ---------------------------------------------------------------- CP-ALS */
 
 /*
@@ -254,6 +296,40 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs /*host*/, con
                                   double *const *lambdas /*host[count] of device ptrs*/, void *stream);
 
 /*
+ * ||X||_F^2 of the tensor (host double; synchronizes the stream).  Duplicate
+ * coordinates count as one entry holding their sum: they are neighbours on
+ * the ordered line, and the norm is the sum over runs of equal ALTO index of
+ * the squared run sum (FP64, fixed order, computed once per handle).
+ */
+alto_status alto_tensor_norm2(alto_handle h, double *norm2 /*host*/, void *stream);
+
+/*
+ * Fit of a CP model, the quantity Algorithm "alg:cp-als" watches:
+ * fit = 1 - ||X - Xhat||_F / ||X||_F with Xhat = sum_r lambda[r] a_r^(0) o ...
+ * o a_r^(N-1), a_r^(m) column r of factors[m] (device FP32 dims[m] x rank;
+ * BF16 shadows are read for the MTTKRP when fdt = ALTO_BF16), lambda device
+ * FP64 [rank].  Evaluated as ||X||^2 + lambda^T (Hadamard of the Grams)
+ * lambda - 2 sum_r lambda_r <M(:, r), A^(N-1)(:, r)>, M the MTTKRP of the last
+ * mode.  *fit (host) receives the value; synchronizes the stream.
+ */
+alto_status alto_cp_fit(alto_handle h, int rank, alto_dtype fdt, float *const *factors, const double *lambda,
+                        double *fit /*host*/, void *stream);
+
+/*
+ * CP-ALS (Algorithm "alg:cp-als"): CP-ALS sweeps on `factors` (in place) until
+ * the fit changes by less than `tol` from one sweep to the next (the fit has
+ * ceased to improve) or `max_sweeps` sweeps have run.  The fit after each
+ * sweep comes from the sweep's own Grams, last-mode MTTKRP and lambda (no
+ * extra MTTKRP).  fits (host [max_sweeps], may be NULL) receives the fit after
+ * each sweep, *sweeps_done (host, may be NULL) the number of sweeps; lambda
+ * (device FP64 [rank]) the last mode's weights.  Blocking: synchronizes the
+ * stream once per sweep to read the fit.  Returns ALTO_ERR_NOT_SPD (results
+ * valid) when any mode update used the pseudo-inverse fallback.
+ */
+alto_status cpd_als(alto_handle h, int rank, alto_dtype fdt, float *const *factors, double *lambda, int max_sweeps,
+                    double tol, double *fits /*host*/, int *sweeps_done /*host*/, void *stream);
+
+/*
  * Status flags of the last sweep on `stream` (host, synchronizes the stream):
  * bit n set when mode n used the pseudo-inverse fallback.
  */
@@ -273,7 +349,12 @@ alto_status alto_sweep_flags(alto_handle h, void *stream, uint32_t *flags /*host
  * Jobs whose footprint exceeds the whole budget are rejected
  * (ALTO_ERR_BUDGET in their completion record).  All pointers in a job are
  * device pointers owned by the caller and must stay valid until the job's
- * completion record has been polled.
+ * completion record has been polled.  The server reads and writes them on
+ * its own streams with no ordering against the caller's streams: every
+ * write that produces a job's inputs must have completed (e.g. the
+ * producing stream synchronized) before alto_server_submit, and the
+ * outputs may be read once the completion record has been polled.  Ranks
+ * are multiples of 4 in 4..64 here (and in the batched calls).
  */
 typedef struct alto_server *alto_server_t;
 

@@ -34,13 +34,53 @@ _lib = None
 MAX_MODES = 16
 
 
+_PAR_SRC = os.path.join(_HERE, "cpu_parallel.c")
+_PAR_LIB = os.path.join(_HERE, "libcpu_parallel.so")
+_par = None
+
+
 def build_oracle(force: bool = True) -> str:
-    """Compile the C oracle with gcc (host only)."""
+    """Compile the C oracle (and the parallel CPU baseline) with gcc (host only)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_PAR_LIB):
+        tmp = _PAR_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-shared", "-fPIC", "-o", tmp,
+                               _PAR_SRC])
+        os.replace(tmp, _PAR_LIB)
     return _LIB
+
+
+def _P():
+    global _par
+    if _par is None:
+        if not os.path.exists(_PAR_LIB):
+            build_oracle(force=True)
+        lib = ctypes.CDLL(_PAR_LIB)
+        P = ctypes.c_void_p
+        lib.par_mttkrp.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, ctypes.c_int, P, ctypes.c_int, P]
+        lib.par_mttkrp.restype = ctypes.c_int
+        lib.par_threads.restype = ctypes.c_int
+        _par = lib
+    return _par
+
+
+def mttkrp_parallel(dims, coords, vals, factors, mode: int):
+    """The parallel CPU baseline (OpenMP over nonzeros, private outputs, in
+    cpu_parallel.c): (output, threads used).  Not part of the checked oracle."""
+    d = _dims(dims)
+    c = np.ascontiguousarray(coords, dtype=np.int64)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    rank = int(np.asarray(factors[0]).shape[1])
+    keep, arr = _factor_ptrs(factors, rank, d)
+    out = np.zeros((int(d[mode]), rank), dtype=np.float64)
+    used = _P().par_mttkrp(len(d), _ptr(d), v.shape[0], _ptr(c), _ptr(v), rank, arr, int(mode), _ptr(out))
+    if used < 0:
+        raise ValueError("invalid mode or rank, or out of memory")
+    del keep
+    return out, used
 
 
 def _L():
@@ -65,6 +105,10 @@ def _L():
         lib.oracle_mttkrp.restype = ctypes.c_int
         lib.oracle_mttkrp_rows.argtypes = [ctypes.c_int, P, i64, P, P, ctypes.c_int, P, ctypes.c_int, i64, P, P]
         lib.oracle_mttkrp_rows.restype = ctypes.c_int
+        lib.oracle_phi.argtypes = [ctypes.c_int, P, i64, P, P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_double, P]
+        lib.oracle_phi.restype = ctypes.c_int
+        lib.oracle_pi.argtypes = [ctypes.c_int, i64, P, ctypes.c_int, P, ctypes.c_int, P]
+        lib.oracle_pi.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -182,6 +226,61 @@ def mttkrp_rows(dims, coords, vals, factors, mode: int, rows) -> np.ndarray:
     return out
 
 
+def mttkrp_abs(dims, coords, vals, factors, mode: int, rows=None) -> np.ndarray:
+    """Entry scale of the MTTKRP sum: S[i, r] = sum over the nonzeros x of row
+    i of |val(x) * prod_{m != mode} A^(m)[i_m(x), r]|, i.e. the MTTKRP of the
+    absolute values.  A floating-point evaluation of the sum in any order with
+    unit roundoff u and at most k roundings per term errs by at most about
+    k*u*S per entry, so S is the per-entry yardstick for rounding error
+    (Higham, "Accuracy and Stability of Numerical Algorithms", ch. 4).
+    ``rows`` restricts it to sampled rows as ``mttkrp_rows`` does."""
+    av = np.abs(np.asarray(vals, dtype=np.float64))
+    af = [np.abs(np.asarray(f, dtype=np.float64)) for f in factors]
+    if rows is None:
+        return mttkrp(dims, coords, av, af, mode)
+    return mttkrp_rows(dims, coords, av, af, mode, rows)
+
+
+def phi(dims, coords, vals, factors, B, mode: int, eps: float) -> np.ndarray:
+    """FP64 CP-APR model update Phi of mode ``mode`` (Algorithm
+    "alg:cp-apr-mu", Phi line): for every nonzero, the Khatri-Rao row krp of
+    the other factors, the model value d = B(i_mode, :) . krp, and
+    Phi(i_mode, :) += v / max(d, eps) * krp.  A plain loop over the COO
+    nonzeros (alto_oracle.c)."""
+    d = _dims(dims)
+    c = np.ascontiguousarray(coords, dtype=np.int64)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    rank = int(np.asarray(B).shape[1])
+    keep, arr = _factor_ptrs([f if m != mode else np.zeros((int(d[m]), rank)) for m, f in enumerate(factors)],
+                             rank, d)
+    b = np.ascontiguousarray(B, dtype=np.float64)
+    if b.shape != (int(d[mode]), rank):
+        raise ValueError("B must be dims[mode] x rank")
+    out = np.zeros((int(d[mode]), rank), dtype=np.float64)
+    rc = _L().oracle_phi(len(d), _ptr(d), v.shape[0], _ptr(c), _ptr(v), rank, arr, _ptr(b), int(mode), float(eps),
+                         _ptr(out))
+    if rc != 0:
+        raise ValueError("invalid mode or rank")
+    del keep
+    return out
+
+
+def pi_rows(dims, coords, factors, mode: int) -> np.ndarray:
+    """Pi of mode ``mode`` restricted to the nonzeros (Algorithm
+    "alg:cp-apr-mu", Pi line): row x = Hadamard product of the other
+    factors' rows at nonzero x, in input order."""
+    d = _dims(dims)
+    c = np.ascontiguousarray(coords, dtype=np.int64)
+    rank = int(np.asarray(factors[0 if mode else 1]).shape[1])
+    keep, arr = _factor_ptrs([f if m != mode else np.zeros((int(d[m]), rank)) for m, f in enumerate(factors)],
+                             rank, d)
+    out = np.zeros((c.shape[1], rank), dtype=np.float64)
+    if _L().oracle_pi(len(d), c.shape[1], _ptr(c), rank, arr, int(mode), _ptr(out)) != 0:
+        raise ValueError("invalid mode or rank")
+    del keep
+    return out
+
+
 def _solve_spd_or_pinv(V: np.ndarray, M: np.ndarray):
     """Return (M V^+, used_cholesky).  V^+ is applied through a Cholesky
     factorisation when V is symmetric positive definite with no pivot
@@ -235,3 +334,53 @@ def als_sweep(dims, coords, vals, factors, return_mttkrp: bool = False):
     if return_mttkrp:
         return A, lam, chol_ok, Ms
     return A, lam, chol_ok
+
+
+def tensor_norm2(dims, coords, vals) -> float:
+    """||X||_F^2 of the tensor the nonzeros add up to: duplicate coordinates
+    are summed first (a nonzero list with repeats stands for their sum)."""
+    c = np.ascontiguousarray(np.asarray(coords, dtype=np.int64).T)
+    v = np.asarray(vals, dtype=np.float64)
+    if v.size == 0:
+        return 0.0
+    _, inv = np.unique(c, axis=0, return_inverse=True)
+    s = np.bincount(inv.ravel(), weights=v)
+    return float(np.dot(s, s))
+
+
+def cp_fit(dims, coords, vals, factors, lam, xnorm2=None) -> float:
+    """Fit 1 - ||X - Xhat||_F / ||X||_F of the CP model
+    Xhat = sum_r lam_r a_r^(0) o ... o a_r^(N-1), the quantity whose
+    improvement Algorithm "alg:cp-als" watches.  Expanded as
+    ||X - Xhat||^2 = ||X||^2 + lam^T (Hadamard of the Grams A^(m)T A^(m)) lam
+    - 2 sum_r lam_r <M(:, r), A^(N-1)(:, r)>, with M the MTTKRP of the last
+    mode (the inner product of X with each rank-one term)."""
+    A = [np.asarray(f, dtype=np.float64) for f in factors]
+    lam = np.asarray(lam, dtype=np.float64)
+    N = len(A)
+    R = A[0].shape[1]
+    xx = tensor_norm2(dims, coords, vals) if xnorm2 is None else float(xnorm2)
+    G = np.ones((R, R))
+    for m in range(N):
+        G *= A[m].T @ A[m]
+    hh = float(lam @ G @ lam)
+    M = mttkrp(dims, coords, vals, A, N - 1)
+    xh = float(np.sum(lam * np.sum(M * A[N - 1], axis=0)))
+    r2 = max(xx + hh - 2.0 * xh, 0.0)
+    return 1.0 - np.sqrt(r2) / np.sqrt(xx) if xx > 0 else 0.0
+
+
+def cp_als(dims, coords, vals, factors, max_sweeps: int, tol: float):
+    """Algorithm "alg:cp-als": CP-ALS sweeps until the fit changes by less
+    than ``tol`` from one sweep to the next ("until fit ceases to improve"),
+    at most ``max_sweeps``.  Returns (factors, lambda, fits per sweep)."""
+    A = [np.array(f, dtype=np.float64, copy=True) for f in factors]
+    xx = tensor_norm2(dims, coords, vals)
+    fits = []
+    lam = np.zeros(A[0].shape[1])
+    for _ in range(max_sweeps):
+        A, lam, _ = als_sweep(dims, coords, vals, A)
+        fits.append(cp_fit(dims, coords, vals, A, lam, xnorm2=xx))
+        if len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
+            break
+    return A, lam, fits

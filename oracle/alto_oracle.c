@@ -264,3 +264,57 @@ int oracle_mttkrp_rows(int nmodes, const uint64_t *dims, int64_t nnz, const int6
     free(t);
     return 0;
 }
+
+/*
+ * CP-APR model update Phi for mode `mode` (Algorithm "alg:cp-apr-mu", the
+ * Phi line; Algorithm "fig:subproblem_algo" for the per-nonzero form):
+ *   for every nonzero x with coordinates i and value v:
+ *     krp[r] = prod over m != mode (ascending m) of A^(m)[i_m, r]
+ *     d      = sum_r B[i_mode, r] * krp[r]         (the model at x)
+ *     out[i_mode, r] += v / max(d, eps) * krp[r]
+ * factors[m] and B (dims[mode] x rank) are row-major; out is overwritten.
+ */
+int oracle_phi(int nmodes, const uint64_t *dims, int64_t nnz, const int64_t *coords, const double *vals, int rank,
+               const double *const *factors, const double *B, int mode, double eps, double *out) {
+    if (mode < 0 || mode >= nmodes || rank < 1) return -1;
+    double *krp = (double *)malloc(sizeof(double) * (size_t)rank);
+    if (!krp) return -1;
+    memset(out, 0, sizeof(double) * (size_t)dims[mode] * (size_t)rank);
+    for (int64_t x = 0; x < nnz; x++) {
+        for (int r = 0; r < rank; r++) krp[r] = 1.0;
+        for (int m = 0; m < nmodes; m++) {
+            if (m == mode) continue;
+            const double *row = factors[m] + (size_t)coords[(int64_t)m * nnz + x] * (size_t)rank;
+            for (int r = 0; r < rank; r++) krp[r] *= row[r];
+        }
+        const int64_t i = coords[(int64_t)mode * nnz + x];
+        const double *b = B + (size_t)i * (size_t)rank;
+        double d = 0.0;
+        for (int r = 0; r < rank; r++) d += b[r] * krp[r];
+        const double s = vals[x] / (d > eps ? d : eps);
+        double *o = out + (size_t)i * (size_t)rank;
+        for (int r = 0; r < rank; r++) o[r] += s * krp[r];
+    }
+    free(krp);
+    return 0;
+}
+
+/*
+ * Rows of Pi for mode `mode`, one per nonzero in input order (the Pi line of
+ * Algorithm "alg:cp-apr-mu", computed only for the nonzeros):
+ *   pi[x, r] = prod over m != mode (ascending m) of A^(m)[i_m(x), r].
+ */
+int oracle_pi(int nmodes, int64_t nnz, const int64_t *coords, int rank, const double *const *factors, int mode,
+              double *pi) {
+    if (mode < 0 || mode >= nmodes || rank < 1) return -1;
+    for (int64_t x = 0; x < nnz; x++) {
+        double *p = pi + (size_t)x * (size_t)rank;
+        for (int r = 0; r < rank; r++) p[r] = 1.0;
+        for (int m = 0; m < nmodes; m++) {
+            if (m == mode) continue;
+            const double *row = factors[m] + (size_t)coords[(int64_t)m * nnz + x] * (size_t)rank;
+            for (int r = 0; r < rank; r++) p[r] *= row[r];
+        }
+    }
+    return 0;
+}

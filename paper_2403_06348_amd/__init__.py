@@ -13,12 +13,12 @@ import ctypes
 
 from . import _capi
 from ._capi import (  # noqa: F401
-    ACC_DEFAULT, ACC_F32, ACC_F64, ACC_XCD_F32, ACC_XCD_F64, BF16, CR_AUTO, CR_DIRECT, CR_RUN, CR_TILE, F32, MttkrpPlan, STATUS_NAMES,
+    ACC_DEFAULT, ACC_F32, ACC_F64, ACC_XCD_F32, ACC_XCD_F64, BF16, CR_AUTO, CR_DIRECT, CR_HOT, CR_RUN, CR_TILE, F32, MttkrpPlan, STATUS_NAMES,
 )
 
 __all__ = [
     "AltoError", "AltoTensor", "plan_dims", "plan_decode_host", "mttkrp_batched", "version", "F32", "BF16",
-    "CR_AUTO", "CR_TILE", "CR_RUN", "CR_DIRECT", "ACC_DEFAULT", "ACC_F64", "ACC_F32", "ACC_XCD_F32", "ACC_XCD_F64",
+    "CR_AUTO", "CR_TILE", "CR_RUN", "CR_DIRECT", "CR_HOT", "ACC_DEFAULT", "ACC_F64", "ACC_F32", "ACC_XCD_F32", "ACC_XCD_F64",
 ]
 
 
@@ -215,6 +215,31 @@ class AltoTensor:
         )
         return out
 
+    # -- CP-APR
+    def cpapr_pi(self, mode: int, factors, out=None, stream=None):
+        """Pi rows of mode ``mode`` for the nonzeros, in ALTO order (nnz x rank)."""
+        torch = _torch()
+        rank = int(next(f for f in factors if f is not None).shape[1])
+        if out is None:
+            out = torch.empty((self.nnz, rank), dtype=torch.float32, device="cuda")
+        _check(_capi.lib().alto_cpapr_pi(self.handle, int(mode), rank, _factor_array(factors, self.nmodes, skip=mode),
+                                         _ptr(out), _stream(stream)), "alto_cpapr_pi")
+        return out
+
+    def cpapr_phi(self, mode: int, factors, B, eps=1e-10, pi=None, out=None, plan=None, stream=None):
+        """CP-APR model update Phi of mode ``mode`` (pi: precomputed Pi rows
+        from cpapr_pi for ALTO-PRE, else ALTO-OTF)."""
+        torch = _torch()
+        rank = int(B.shape[1])
+        if out is None:
+            out = torch.empty((self.dims[mode], rank), dtype=torch.float32, device="cuda")
+        farr = _factor_array(factors, self.nmodes, skip=mode) if factors is not None else None
+        p = _plan_struct(plan)
+        _check(_capi.lib().alto_cpapr_phi(self.handle, int(mode), rank, farr, _ptr(B), float(eps), _ptr(pi),
+                                          _ptr(out), ctypes.byref(p) if p else None, _stream(stream)),
+               "alto_cpapr_phi")
+        return out
+
     def get_plan(self, mode: int, rank: int, fdt=F32) -> dict:
         p = MttkrpPlan()
         _check(_capi.lib().alto_mttkrp_get_plan(self.handle, int(mode), int(rank), int(fdt), ctypes.byref(p)),
@@ -248,6 +273,37 @@ class AltoTensor:
             "cpd_als_sweep",
         )
         return lam
+
+    def norm2(self, stream=None) -> float:
+        """||X||_F^2 of the tensor (duplicates summed)."""
+        v = ctypes.c_double()
+        _check(_capi.lib().alto_tensor_norm2(self.handle, ctypes.byref(v), _stream(stream)), "alto_tensor_norm2")
+        return float(v.value)
+
+    def fit(self, factors, lam, fdt=F32, stream=None) -> float:
+        """Fit 1 - ||X - Xhat|| / ||X|| of the CP model (lam, factors)."""
+        rank = int(factors[0].shape[1])
+        farr = (ctypes.c_void_p * self.nmodes)(*[f.data_ptr() for f in factors])
+        v = ctypes.c_double()
+        _check(_capi.lib().alto_cp_fit(self.handle, rank, int(fdt), farr, _ptr(lam), ctypes.byref(v),
+                                       _stream(stream)), "alto_cp_fit")
+        return float(v.value)
+
+    def cp_als(self, factors, max_sweeps, tol, lam=None, fdt=F32, stream=None):
+        """CP-ALS until the fit improves by less than ``tol`` (at most
+        ``max_sweeps`` sweeps).  Returns (lambda, fits per sweep, used the
+        pseudo-inverse)."""
+        torch = _torch()
+        rank = int(factors[0].shape[1])
+        if lam is None:
+            lam = torch.empty(rank, dtype=torch.float64, device="cuda")
+        farr = (ctypes.c_void_p * self.nmodes)(*[f.data_ptr() for f in factors])
+        fits = (ctypes.c_double * max_sweeps)()
+        done = ctypes.c_int()
+        st = _check(_capi.lib().cpd_als(self.handle, rank, int(fdt), farr, _ptr(lam), int(max_sweeps),
+                                        float(tol), fits, ctypes.byref(done), _stream(stream)),
+                    "cpd_als", allow=(_capi.ERR_NOT_SPD,))
+        return lam, [float(fits[k]) for k in range(done.value)], st == _capi.ERR_NOT_SPD
 
     def sweep_flags(self, stream=None) -> int:
         f = ctypes.c_uint32()

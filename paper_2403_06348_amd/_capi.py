@@ -33,6 +33,7 @@ CR_AUTO = 0
 CR_TILE = 1
 CR_RUN = 2
 CR_DIRECT = 3
+CR_HOT = 4
 
 ACC_DEFAULT = 0
 ACC_F64 = 1
@@ -146,6 +147,11 @@ SIGNATURES = {
     "cpd_als_sweep": (I32, [P, I32, P, P, P]),
     "cpd_als_sweep_ex": (I32, [P, I32, I32, P, P, P]),
     "alto_sweep_flags": (I32, [P, P, ctypes.POINTER(ctypes.c_uint32)]),
+    "alto_tensor_norm2": (I32, [P, ctypes.POINTER(ctypes.c_double), P]),
+    "alto_cpapr_phi": (I32, [P, I32, I32, P, P, ctypes.c_float, P, P, ctypes.POINTER(MttkrpPlan), P]),
+    "alto_cpapr_pi": (I32, [P, I32, I32, P, P, P]),
+    "alto_cp_fit": (I32, [P, I32, I32, P, P, ctypes.POINTER(ctypes.c_double), P]),
+    "cpd_als": (I32, [P, I32, I32, P, P, I32, ctypes.c_double, P, ctypes.POINTER(I32), P]),
     "cpd_als_sweep_batched": (I32, [I32, P, P, P, P, P, P]),
     "alto_server_create": (I32, [U64, I32, ctypes.POINTER(P)]),
     "alto_server_submit": (I32, [P, ctypes.POINTER(ServeJob)]),

@@ -32,7 +32,7 @@ namespace alto {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPartials = 512;    // partial Gram blocks
+constexpr int kPartials = kSweepPartials;  // partial Gram blocks
 constexpr int kMaxSweepRank = 64;
 constexpr int kMaxPairs = kMaxSweepRank / 2;  // Jacobi rotations per step
 static_assert(kThreads == 8 * kMaxPairs && kMaxSweepRank <= 64, "Jacobi step thread layout: 32 x 8 blocks, 4 x 64 Q rows");
@@ -257,8 +257,13 @@ inline unsigned gram_reduce_blocks(int R) { return (unsigned)((R * R + 63) / 64)
 // LDS of the solve preparation: three R x R FP64 matrices, row stride R + 1.
 inline size_t prepare_lds_bytes(int R) { return (size_t)3 * R * (R + 1) * sizeof(double); }
 
-__device__ inline void als_prepare(const double *__restrict__ grams, int N, int n, int R, double *__restrict__ W,
-                                   uint32_t *flags, double *sm) {
+// Rt <= R: the model's true rank.  Columns Rt..R-1 are zero padding (ranks
+// are stored as multiples of 4); their Gram rows and columns are zero, so V
+// gets an identity block scaled to its largest diagonal entry there: the
+// solve then leaves the padding columns of A = M V^-1 at zero (M is zero
+// there too) and the true block is solved exactly as without padding.
+__device__ inline void als_prepare(const double *__restrict__ grams, int N, int n, int R, int Rt,
+                                   double *__restrict__ W, uint32_t *flags, double *sm) {
     // R x R matrices in LDS with row stride R + 1: walks down a column then
     // touch every bank instead of one
     const int LD = R + 1;
@@ -270,8 +275,12 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
     const int tid = threadIdx.x;
     for (int e = tid; e < R * R; e += kThreads) {
         double v = 1.0;
-        for (int m = 0; m < N; m++)
-            if (m != n) v *= grams[(uint64_t)m * R * R + e];
+        if (e / R < Rt && e % R < Rt) {
+            for (int m = 0; m < N; m++)
+                if (m != n) v *= grams[(uint64_t)m * R * R + e];
+        } else {
+            v = 0.0;
+        }
         V[(e / R) * LD + e % R] = v;
         L[(e / R) * LD + e % R] = 0.0;
     }
@@ -279,8 +288,9 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
     __syncthreads();
     if (tid == 0) {
         double mx = 0.0;
-        for (int k = 0; k < R; k++) mx = fmax(mx, V[k * LD + k]);
+        for (int k = 0; k < Rt; k++) mx = fmax(mx, V[k * LD + k]);
         vmax = mx;
+        for (int k = Rt; k < R; k++) V[k * LD + k] = mx > 0.0 ? mx : 1.0;
     }
     __syncthreads();
     const double tol = (double)R * 2.220446049250313e-16 * vmax;
@@ -493,9 +503,9 @@ __device__ inline void als_prepare(const double *__restrict__ grams, int N, int 
 }
 
 __global__ __launch_bounds__(kThreads) void k_als_prepare(const double *__restrict__ grams, int N, int n, int R,
-                                                          double *__restrict__ W, uint32_t *flags) {
+                                                          int Rt, double *__restrict__ W, uint32_t *flags) {
     extern __shared__ double sm[];
-    als_prepare(grams, N, n, R, W, flags, sm);
+    als_prepare(grams, N, n, R, Rt, W, flags, sm);
 }
 
 // Gn holds the Gram of the updated (unnormalized) factor: lambda = the
@@ -560,7 +570,7 @@ struct SweepJob {
 __global__ __launch_bounds__(kThreads) void k_als_prepare_b(const SweepJob *__restrict__ jobs) {
     extern __shared__ double sm[];
     const SweepJob &j = jobs[blockIdx.x];
-    als_prepare(j.grams, j.N, j.n, j.R, j.W, j.flags, sm);
+    als_prepare(j.grams, j.N, j.n, j.R, j.R, j.W, j.flags, sm);
 }
 
 __global__ __launch_bounds__(kThreads) void k_gram_reduce_b(const SweepJob *__restrict__ jobs) {
@@ -646,7 +656,7 @@ alto_status sweep_setup(alto_tensor *h, int rank, int fdt, float *const *factors
     ALTO_CHECK_HANDLE(h);
     const int N = h->info.nmodes;
     const int R = rank;
-    if (R < 4 || R > kMaxSweepRank || R % 4) return fail(ALTO_ERR_ARG, "sweep rank must be a multiple of 4 in 4..64");
+    if (R < 4 || R > kMaxSweepRank || R % 4) return fail(ALTO_ERR_ARG, "sweep rank must be in 1..64");
     if (fdt != ALTO_F32 && fdt != ALTO_BF16) return fail(ALTO_ERR_ARG, "bad factor dtype");
     if (!factors || !lambda) return fail(ALTO_ERR_ARG, "factors/lambda is NULL");
     for (int m = 0; m < N; m++) {
@@ -709,12 +719,12 @@ void sweep_factor_ptrs(const alto_tensor *h, int fdt, float *const *factors, con
         fptr[m] = fdt == ALTO_BF16 ? (const void *)h->ws_bf16[m] : (const void *)factors[m];
 }
 
-alto_status sweep_pre(alto_tensor *h, int n, int rank, hipStream_t s) {
+alto_status sweep_pre(alto_tensor *h, int n, int rank, int rank_true, hipStream_t s) {
     const size_t rr = (size_t)rank * rank;
     double *grams = (double *)h->ws_sweep;
     double *W = grams + h->info.nmodes * rr;
-    hipLaunchKernelGGL(k_als_prepare, dim3(1), dim3(kThreads), prepare_lds_bytes(rank), s, grams, h->info.nmodes, n, rank, W,
-                       h->ws_flags);
+    hipLaunchKernelGGL(k_als_prepare, dim3(1), dim3(kThreads), prepare_lds_bytes(rank), s, grams, h->info.nmodes, n, rank,
+                       rank_true, W, h->ws_flags);
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
 }
@@ -739,21 +749,14 @@ alto_status sweep_post(alto_tensor *h, int n, int rank, int fdt, float *const *f
     return ALTO_OK;
 }
 
-}  // namespace alto
-
-using namespace alto;
-
-extern "C" {
-
-alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *const *factors, double *lambda,
-                             void *stream) {
-    hipStream_t s = (hipStream_t)stream;
+alto_status sweep_run(alto_tensor *h, int rank, int rank_true, int fdt, float *const *factors, double *lambda,
+                      hipStream_t s) {
     alto_status st = sweep_begin(h, rank, fdt, factors, lambda, s);
     if (st != ALTO_OK) return st;
     const void *fptr[ALTO_MAX_MODES];
     sweep_factor_ptrs(h, fdt, factors, fptr);
     for (int n = 0; n < h->info.nmodes; n++) {
-        st = sweep_pre(h, n, rank, s);
+        st = sweep_pre(h, n, rank, rank_true, s);
         if (st != ALTO_OK) return st;
         alto_mttkrp_plan p;
         st = resolve_plan(h, n, rank, fdt, nullptr, &p);
@@ -763,6 +766,34 @@ alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *con
         st = sweep_post(h, n, rank, fdt, factors, n == h->info.nmodes - 1 ? lambda : nullptr, s);
         if (st != ALTO_OK) return st;
     }
+    return ALTO_OK;
+}
+
+}  // namespace alto
+
+using namespace alto;
+
+extern "C" {
+
+alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *const *factors, double *lambda,
+                             void *stream) {
+    ALTO_CHECK_HANDLE(h);
+    hipStream_t s = (hipStream_t)stream;
+    if (rank % 4 == 0 || rank < 1) return sweep_run(h, rank, rank, fdt, factors, lambda, s);
+    // a rank that is not a multiple of 4: sweep zero-padded copies
+    if (rank > kMaxSweepRank) return fail(ALTO_ERR_ARG, "sweep rank must be in 1..64");
+    if (!factors || !lambda) return fail(ALTO_ERR_ARG, "factors/lambda is NULL");
+    const int R4 = padded_rank(rank);
+    void *pf[ALTO_MAX_MODES];
+    alto_status st = pad_factors(h, rank, ALTO_F32, (const void *const *)factors, -1, pf, s);
+    if (st != ALTO_OK) return st;
+    st = ensure_ws((void **)&h->ws_lampad, &h->ws_lampad_bytes, (size_t)R4 * sizeof(double));
+    if (st != ALTO_OK) return st;
+    st = sweep_run(h, R4, rank, fdt, (float *const *)pf, h->ws_lampad, s);
+    if (st != ALTO_OK) return st;
+    for (int m = 0; m < h->info.nmodes; m++) launch_copy_cols(pf[m], R4, factors[m], rank, h->info.dims[m], 4, s);
+    ALTO_HIP(hipMemcpyAsync(lambda, h->ws_lampad, (size_t)rank * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ALTO_HIP(hipGetLastError());
     return ALTO_OK;
 }
 

@@ -92,6 +92,16 @@ struct alto_tensor {
     uint16_t *ws_bf16[ALTO_MAX_MODES];  // BF16 shadows of the factors
     size_t ws_bf16_bytes[ALTO_MAX_MODES];
     uint32_t *ws_flags;    // CP-ALS status flags (device)
+    // ranks that are not a multiple of 4 run on zero-padded copies
+    void *ws_pad[ALTO_MAX_MODES];  // factors with rank rounded up to a multiple of 4
+    size_t ws_pad_bytes[ALTO_MAX_MODES];
+    float *ws_pad_out;             // MTTKRP output of the padded rank
+    size_t ws_pad_out_bytes;
+    double *ws_lampad;             // lambda of the padded rank
+    size_t ws_lampad_bytes;
+    double *ws_fit;        // fit: [0] = ||X||^2 of the summed tensor, [1] = last fit (device)
+    size_t ws_fit_bytes;
+    bool xnorm_ready;      // ws_fit[0] holds ||X||^2
     // per (mode, rank, dtype) tuned plans
     alto_mttkrp_plan tuned[ALTO_MAX_MODES][2][33];
     bool has_tuned[ALTO_MAX_MODES][2][33];

@@ -50,7 +50,9 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
         p.conflict = ALTO_CR_TILE;
         p.rank_tile = 0;
         p.accumulate = ALTO_ACC_F32;
-        p.tile_nnz = tile;
+        // FP32 atomics into the output: a row takes at most one addition per
+        // tile, so long tensors get longer tiles (see accuracy_policy)
+        p.tile_nnz = (int)std::max<uint64_t>((uint64_t)tile, (h->info.nnz + kBatchF32MaxTiles - 1) / kBatchF32MaxTiles);
         p.table_slots = std::max(16, p.table_slots * slots_factor / 2);
         // one LDS size serves the whole launch: keep every table within
         // 96 KiB of FP64 rows, keys and hit counts
@@ -204,11 +206,34 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
     alto_status st = check_mttkrp_args(h, mode, rank, fdt, factors, out);
     if (st != ALTO_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    if (rank % 4 == 0) return autotune_run(h, mode, rank, fdt, factors, out, s, chosen);
+    // a rank that is not a multiple of 4 is tuned (and later run) padded
+    const int R4 = padded_rank(rank);
+    void *pf[ALTO_MAX_MODES];
+    st = pad_factors(h, rank, fdt, factors, mode, pf, s);
+    if (st != ALTO_OK) return st;
+    st = ensure_ws((void **)&h->ws_pad_out, &h->ws_pad_out_bytes, h->info.dims[mode] * (size_t)R4 * 4);
+    if (st != ALTO_OK) return st;
+    st = autotune_run(h, mode, R4, fdt, (const void *const *)pf, h->ws_pad_out, s, chosen);
+    if (st != ALTO_OK) return st;
+    launch_copy_cols(h->ws_pad_out, R4, out, rank, h->info.dims[mode], 4, s);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+}  // extern "C"
+
+namespace alto {
+
+// The autotuner proper, at a rank that is a multiple of 4.
+alto_status autotune_run(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
+                         hipStream_t s, alto_mttkrp_plan *chosen) {
+    alto_status st = ALTO_OK;
     const alto_mttkrp_plan base = default_plan(h, mode, rank, fdt);
     std::vector<alto_mttkrp_plan> cands;
     const uint64_t nnz = h->info.nnz;
     for (int threads : {256, 512}) {
-        for (int tile : {2048, 4096, 8192, 16384, 32768}) {
+        for (int tile : {2048, 4096, 8192, 16384, 32768, 65536}) {
             if (nnz > 0 && (uint64_t)tile * 64 > nnz && tile != base.tile_nnz) continue;  // keep >= 64 tiles
             for (int f : {1, 2, 4}) {
                 alto_mttkrp_plan p = base;
@@ -263,6 +288,7 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
     ALTO_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     alto_mttkrp_plan bestp = base;
+    for (auto &p : cands) accuracy_policy(h, mode, rank, &p);
     for (const auto &p : cands) {
         st = run_mttkrp(h, mode, rank, fdt, factors, out, p, s);  // warm
         if (st != ALTO_OK) break;
@@ -290,6 +316,10 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
     return ALTO_OK;
 }
 
+}  // namespace alto
+
+extern "C" {
+
 alto_status alto_mttkrp_batched(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
                                 const void *const *const *factors, float *const *outs, void *stream) {
     if (count < 0) return fail(ALTO_ERR_ARG, "count < 0");
@@ -299,6 +329,7 @@ alto_status alto_mttkrp_batched(int count, const alto_handle *hs, const int *mod
         if (!factors[j]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(j) + "] is NULL");
         alto_status st = check_mttkrp_args(hs[j], modes[j], ranks[j], fdts[j], factors[j], outs[j]);
         if (st != ALTO_OK) return fail(st, "item " + std::to_string(j) + ": " + alto_last_error());
+        if (ranks[j] % 4) return fail(ALTO_ERR_ARG, "item " + std::to_string(j) + ": batched ranks must be multiples of 4");
     }
     return batched_run(count, hs, modes, ranks, fdts, factors, outs, (hipStream_t)stream);
 }

@@ -534,7 +534,9 @@ alto_status alto_build(int nmodes, const uint64_t *dims, uint64_t nnz, const int
 alto_status alto_info(alto_handle h, alto_info_t *out) {
     ALTO_CHECK_HANDLE(h);
     if (!out) return fail(ALTO_ERR_ARG, "out is NULL");
-    size_t ws = dev_size(h->ws_acc) + dev_size(h->ws_sweep) + dev_size(h->ws_m) + dev_size(h->ws_flags);
+    size_t ws = dev_size(h->ws_acc) + dev_size(h->ws_sweep) + dev_size(h->ws_m) + dev_size(h->ws_flags) +
+                dev_size(h->ws_fit) + dev_size(h->ws_pad_out) + dev_size(h->ws_lampad);
+    for (int n = 0; n < ALTO_MAX_MODES; n++) ws += dev_size(h->ws_pad[n]);
     for (int n = 0; n < ALTO_MAX_MODES; n++) ws += dev_size(h->ws_bf16[n]);
     h->info.device_bytes = dev_size(h->keys) + dev_size(h->vals) + ws;
     *out = h->info;
@@ -590,6 +592,10 @@ alto_status alto_free(alto_handle h) {
     dev_free(h->ws_sweep);
     dev_free(h->ws_m);
     dev_free(h->ws_flags);
+    dev_free(h->ws_fit);
+    dev_free(h->ws_pad_out);
+    dev_free(h->ws_lampad);
+    for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free(h->ws_pad[n]);
     for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free(h->ws_bf16[n]);
     h->magic = 0;
     delete h;

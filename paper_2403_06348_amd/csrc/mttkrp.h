@@ -36,6 +36,11 @@ struct MttkrpArgs {
     uint32_t ld;      // row stride of factors and output (the full rank)
     uint32_t col0;    // first column of this rank tile
     uint64_t copy_stride;  // elements per copy
+    // CP-APR Phi forms: B (dims[mode] x ld FP32), Pi (nnz x ld FP32, ALTO
+    // order; ALTO-PRE only), the divisor floor eps
+    const float *phi_B;
+    const float *phi_pi;
+    float phi_eps;
 };
 
 constexpr int kXcdCopies = 8;  // XCDs of an MI355X
@@ -44,11 +49,17 @@ alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt)
 void record_tuned(alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan &p);
 alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan *in,
                          alto_mttkrp_plan *out);
+// FP32-atomic plans whose rows would take too many additions sum in per-XCD
+// FP32 copies or in FP64 instead (see mttkrp.hip); accumulate modes other
+// than ALTO_ACC_F32 are left alone.
+void accuracy_policy(const alto_tensor *h, int mode, int rank, alto_mttkrp_plan *p);
+constexpr uint64_t kBatchF32MaxTiles = 2048;  // batched launches: tiles per job at most
 alto_status check_mttkrp_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
                               const float *out);
 alto_status ensure_ws(void **p, size_t *have, size_t need);
+// acc_buf: accumulation buffer for FP64 / per-XCD plans (NULL: handle workspace)
 alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
-                       const alto_mttkrp_plan &p, hipStream_t s);
+                       const alto_mttkrp_plan &p, hipStream_t s, void *acc_buf = nullptr);
 void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
                const alto_mttkrp_plan &p, float *out32, double *out64, MttkrpArgs *a, int col0 = 0,
                int rank_tile = 0);
@@ -56,6 +67,12 @@ size_t lds_bytes(const MttkrpArgs &a, int threads);
 int lpn_for(int rank);
 int pow2_floor(int v);
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s);
+// Persistent launch of a stretch kernel (grid = CUs x occupancy, XCD-ordered
+// stretches), timed when timing is enabled.
+alto_status launch_stretch_kernel(const alto_tensor *h, const void *kern, const MttkrpArgs &a, int threads,
+                                  hipStream_t s);
+// LDS bytes beyond the tables a stretch kernel may use (static arrays).
+size_t static_lds_allowance();
 const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch);
 const void *pick_single(int lpn, int fdt, int words, const MttkrpArgs &a);
 // Largest whole-mode LDS table (bytes) a workgroup of `threads` can hold
@@ -70,17 +87,44 @@ bool tile_plan_fits(const alto_tensor *h, int rank_tile, int slots, int threads)
 alto_status check_launch_lds(const void *kern, size_t dyn, int dev);
 const void *zero_outputs_kernel();
 int device_cus(int dev);
+size_t device_lds(int dev);  // LDS bytes one workgroup may allocate
 
 // batched MTTKRP (batch.hip), arguments already validated
 alto_status batched_run(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
                         const void *const *const *factors, float *const *outs, hipStream_t s);
 
+// Ranks that are not a multiple of 4: the library works on copies whose rows
+// are padded with zero columns to the next multiple of 4 (mttkrp.hip).
+inline int padded_rank(int rank) { return (rank + 3) & ~3; }
+// dst (I x ldd) = src (I x lds) in columns [0, lds), zero in [lds, ldd);
+// esize 2 or 4 bytes.  Also used the other way (ldd < lds) to copy back.
+void launch_copy_cols(const void *src, int lds, void *dst, int ldd, uint64_t I, int esize, hipStream_t s);
+// Zero-padded copies of factors[m] (m != skip) in the handle's pad
+// workspace; fptr[m] receives them.
+alto_status pad_factors(alto_tensor *h, int rank, int fdt, const void *const *factors, int skip, void **fptr,
+                        hipStream_t s);
+
+// The autotuner at a rank that is a multiple of 4 (batch.hip).
+alto_status autotune_run(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
+                         hipStream_t s, alto_mttkrp_plan *chosen);
+
 // CP-ALS sweep phases (als.hip)
 alto_status sweep_begin(alto_tensor *h, int rank, int fdt, float *const *factors, const double *lambda, hipStream_t s);
 void sweep_factor_ptrs(const alto_tensor *h, int fdt, float *const *factors, const void **fptr);
-alto_status sweep_pre(alto_tensor *h, int n, int rank, hipStream_t s);
+alto_status sweep_pre(alto_tensor *h, int n, int rank, int rank_true, hipStream_t s);
+// One sweep at a rank that is a multiple of 4, of which the first rank_true
+// columns are the model (the others zero padding).
+alto_status sweep_run(alto_tensor *h, int rank, int rank_true, int fdt, float *const *factors, double *lambda,
+                      hipStream_t s);
 alto_status sweep_post(alto_tensor *h, int n, int rank, int fdt, float *const *factors, double *lambda,
                        hipStream_t s);
+// CP fit (fit.hip): ||X||^2 once per handle into h->ws_fit[0]; the fit of the
+// model left in the sweep workspace (Grams, last mode's MTTKRP in ws_m).
+alto_status ensure_xnorm2(alto_tensor *h, hipStream_t s);
+alto_status launch_fit(alto_tensor *h, int rank, const float *A_last, const double *lam, double *fit, hipStream_t s);
+// Partial R x R Grams the sweep workspace holds (after the Grams and the
+// solve operator); the fit's column dot products reuse that area.
+constexpr int kSweepPartials = 512;
 bool timing_begin(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1);
 void timing_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 

@@ -47,8 +47,29 @@ class Server:
 
     def submit(self, tag, dims, coords, vals, factors, lam, rank, sweeps, fdt=F32):
         """coords: list of CUDA int64 tensors; vals CUDA float32; factors list of
-        CUDA float32 (dims[m], rank), updated in place; lam CUDA float64."""
+        CUDA float32 (dims[m], rank), updated in place; lam CUDA float64.
+
+        The server reads and writes these buffers on its own streams, so the
+        caller's current stream is synchronized first: whatever it enqueued to
+        produce them has finished when the job is queued."""
+        import torch
+
         nnz = int(vals.shape[0])
+        n = len(dims)
+        if len(coords) != n or len(factors) != n:
+            raise ValueError("coords and factors need one tensor per mode")
+        for c in coords:
+            if not (c.is_cuda and c.dtype == torch.int64 and c.is_contiguous() and c.numel() == nnz):
+                raise TypeError("coords must be contiguous CUDA int64 tensors of nnz entries")
+        if not (vals.is_cuda and vals.dtype == torch.float32 and vals.is_contiguous() and vals.dim() == 1):
+            raise TypeError("vals must be a contiguous CUDA float32 vector")
+        for m, f in enumerate(factors):
+            if not (f.is_cuda and f.dtype == torch.float32 and f.is_contiguous()
+                    and tuple(f.shape) == (int(dims[m]), int(rank))):
+                raise TypeError(f"factors[{m}] must be a contiguous CUDA float32 ({dims[m]}, {rank}) tensor")
+        if not (lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous() and lam.numel() >= int(rank)):
+            raise TypeError("lam must be a contiguous CUDA float64 tensor of rank entries")
+        torch.cuda.current_stream().synchronize()
         j = _job_struct(dims, nnz, coords, vals, factors, lam, rank, sweeps, fdt, tag)
         self._keep[int(tag)] = (coords, vals, factors, lam)
         _check(_capi.lib().alto_server_submit(self._h, ctypes.byref(j)), "alto_server_submit")

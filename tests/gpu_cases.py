@@ -69,4 +69,34 @@ def bf16_round(a: np.ndarray) -> np.ndarray:
 
 
 __all__ = ["CASES", "case", "say", "upload", "rel_fro", "factors_for", "vals32", "bf16_round",
-           "random_small_tensor"]
+           "random_small_tensor", "ENTRY_TOL", "entrywise_excess", "assert_entrywise"]
+
+
+# Per-entry parity.  A relative Frobenius bound over a whole MTTKRP result
+# is dominated by the heaviest rows of a skewed tensor: thousands of light
+# rows could be wrong (even zero) and still pass it.  Every entry is held
+# to ENTRY_TOL times its own scale S = sum over its terms of |v * prod A|
+# (oracle.mttkrp_abs), with a tiny absolute floor for empty rows.
+ENTRY_TOL = 1e-5
+ENTRY_FLOOR = 1e-30
+
+
+def entrywise_excess(got, ref, scale, tol=ENTRY_TOL):
+    """(count of entries beyond tol*scale + floor, worst |got-ref| / (tol*scale + floor))."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    lim = tol * np.asarray(scale, dtype=np.float64) + ENTRY_FLOOR
+    ratio = np.abs(got - ref) / lim
+    return int(np.count_nonzero(ratio > 1.0)), float(ratio.max()) if ratio.size else 0.0
+
+
+def assert_entrywise(got, ref, scale, tol=ENTRY_TOL, what=""):
+    nbad, worst = entrywise_excess(got, ref, scale, tol)
+    if nbad:
+        g = np.asarray(got, dtype=np.float64)
+        r = np.asarray(ref, dtype=np.float64)
+        sc = np.asarray(scale, dtype=np.float64)
+        k = np.unravel_index(np.argmax(np.abs(g - r) / (tol * sc + ENTRY_FLOOR)), r.shape)
+        detail = f"worst at {tuple(int(i) for i in k)}: got {g[k]!r} ref {r[k]!r} scale {sc[k]!r}"
+        raise AssertionError(f"{what}: {nbad} entries beyond {tol:g} x their scale (worst {worst:.2f}x); {detail}")
+    return worst

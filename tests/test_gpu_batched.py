@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_cases import rel_fro, say, vals32
+from gpu_cases import assert_entrywise, rel_fro, say, vals32
+from sweep_check import check_sweep
 from synth import make_factors, zipf_tensor
 
 pytestmark = pytest.mark.gpu
@@ -57,6 +58,9 @@ def test_batched_matches_oracle_and_alone():
             alone = T.mttkrp(mode, gf).cpu().numpy().astype(np.float64)
             say(f"    item {k}: nnz={X.nnz} N={X.nmodes} R={R} mode={mode} err {e:.2e}")
             assert e <= 1e-5
+            S = oracle.mttkrp_abs(X.dims, X.coords, vals32(X).astype(np.float64),
+                                  [f.astype(np.float64) for f in facs], mode)
+            assert_entrywise(got, ref, S, what=f"batched item {k}")
             assert rel_fro(got, alone) <= 2e-6
     for X, T, *_ in jobs:
         T.free()
@@ -91,6 +95,11 @@ def test_batched_sweep_matches_separate_sweeps():
     say(f"[batched] sweep of {len(items)} tensors")
     alto.sweep_batched(items)
     torch.cuda.synchronize()
+    for k, (it, (X, T, facs, R)) in enumerate(zip(items, jobs)):
+        # each mode of each tensor against the oracle's update from the
+        # factors that mode saw
+        check_sweep(X.dims, X.coords, vals32(X), [f.cpu().numpy() for f in facs],
+                    [f.cpu().numpy() for f in it[1]], it[2].cpu().numpy(), what=f"batched item {k}")
     for k, (it, (fa, lam)) in enumerate(zip(items, alone)):
         for n in range(len(fa)):
             e = rel_fro(it[1][n].cpu().numpy().astype(np.float64), fa[n].cpu().numpy().astype(np.float64))

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from gpu_cases import rel_fro, say
+from sweep_check import check_sweep
 from synth.serving import assign_arrivals, job_stream, make_job_tensors
 
 pytestmark = pytest.mark.gpu
@@ -55,7 +56,7 @@ def test_served_results_equal_alone_and_budget_holds():
         S.submit(j.tag, j.dims, coords, vals, f, lam, j.rank, SWEEPS)
     # a job whose footprint exceeds the whole budget
     big_dims = (4_000_000, 4_000_000, 4_000_000)
-    bf = [torch.zeros((4, 4), device="cuda")] * 3
+    bf = [torch.zeros((d, 4), device="cuda") for d in big_dims]
     S.submit(999, big_dims, [torch.zeros(1, dtype=torch.int64, device="cuda")] * 3,
              torch.zeros(1, device="cuda"), bf, torch.zeros(4, dtype=torch.float64, device="cuda"), 4, 1)
     S.drain()
@@ -80,4 +81,38 @@ def test_served_results_equal_alone_and_budget_holds():
             # single launch; each sweep amplifies it by cond(V)
             assert e <= 2e-3, (j.tag, n, e)
         assert rel_fro(lam.cpu().numpy(), la) <= 2e-3
+    S.close()
+
+
+def test_served_sweeps_match_oracle_per_mode():
+    """One sweep per job, in a mix whose admission the budget limits: every
+    mode of every served job against the oracle's update from the factors
+    that mode saw (the stated 1e-5 MTTKRP bound, inside the mix)."""
+    jobs = assign_arrivals(job_stream(count=10, seed=13, dim_hi=3e4, nnz_hi=1.5e5), rate_per_s=300.0)
+    data = {j.tag: make_job_tensors(j) for j in jobs}
+    fps = [serve.footprint(j.dims, j.nnz, j.rank) for j in jobs]
+    S = serve.Server(budget_bytes=int(max(fps) * 2.5), max_active=4)
+    start, mixed = {}, {}
+    t0 = time.perf_counter()
+    for j in jobs:
+        while time.perf_counter() - t0 < j.arrival_s:
+            time.sleep(0.0005)
+        coords, vals, facs = data[j.tag]
+        start[j.tag] = [x.cpu().numpy() for x in facs]
+        f = [x.clone() for x in facs]
+        lam = torch.empty(j.rank, dtype=torch.float64, device="cuda")
+        mixed[j.tag] = (f, lam)
+        S.submit(j.tag, j.dims, coords, vals, f, lam, j.rank, 1)
+    S.drain()
+    done = {d["user_tag"]: d for d in S.poll()}
+    st = S.stats()
+    say(f"[serve] per-mode run: {st}")
+    assert st["completed"] == len(jobs)
+    assert st["bytes_peak"] <= int(max(fps) * 2.5)
+    for j in jobs:
+        assert done[j.tag]["status"] == 0
+        coords, vals, _ = data[j.tag]
+        f, lam = mixed[j.tag]
+        check_sweep(j.dims, np.stack([c.cpu().numpy() for c in coords]), vals.cpu().numpy(), start[j.tag],
+                    [x.cpu().numpy() for x in f], lam.cpu().numpy(), what=f"served job {j.tag}")
     S.close()

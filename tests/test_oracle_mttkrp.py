@@ -231,3 +231,14 @@ def test_als_pseudoinverse_fallback_is_min_norm_least_squares():
     sol = (np.linalg.pinv(K) @ unfold(dense_of(X.dims, X.coords, X.vals), 0).T).T
     lam0 = np.linalg.norm(sol, axis=0)
     np.testing.assert_allclose(A[0], sol / lam0, rtol=1e-7, atol=1e-9)
+
+
+def test_parallel_cpu_baseline_equals_oracle():
+    """The benchmark's parallel CPU leg computes the oracle's result."""
+    X = make_config("c1")
+    facs = make_factors(X.dims, 8, seed=2)
+    for n in range(3):
+        ref = oracle.mttkrp(X.dims, X.coords, X.vals, facs, n)
+        got, used = oracle.mttkrp_parallel(X.dims, X.coords, X.vals, facs, n)
+        assert used >= 1
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
