@@ -206,6 +206,24 @@ alto_status alto_mttkrp(alto_handle h, int mode, int rank, alto_dtype fdt, const
 alto_status alto_mttkrp_ex(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors,
                            float *out, const alto_mttkrp_plan *plan, void *stream);
 
+/*
+ * Allocation-free MTTKRP, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): alto_mttkrp_ex with FP64 accumulation (ALTO_ACC_F64), whose
+ * accumulation buffer is a static device array of the library instead of
+ * handle workspace.  Nothing is allocated: no hipMalloc, hipFree or
+ * allocating library routine.  Limits: rank a multiple of 4 and
+ * dims[mode] * rank <= 8,388,608 (the array holds 2^23 doubles, 64 MiB, on
+ * every GPU the library runs on, until the process ends); larger requests
+ * fail with ALTO_ERR_ARG.  plan->accumulate must be 0 or ALTO_ACC_F64.  The
+ * handle's device must be the current device.  All calls on one GPU share
+ * the array: calls that overlap in time on one GPU (other streams, other
+ * threads) race and give wrong results; calls on one stream are ordered.
+ * The array is cleared by each call before use.
+ */
+alto_status alto_mttkrp_noalloc(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors,
+                                float *out, const alto_mttkrp_plan *plan, void *stream);
+
 /* Plan that alto_mttkrp would use for (mode, rank, fdt) (host). */
 alto_status alto_mttkrp_get_plan(alto_handle h, int mode, int rank, alto_dtype fdt, alto_mttkrp_plan *out);
 

@@ -142,6 +142,7 @@ SIGNATURES = {
     "alto_mttkrp": (I32, [P, I32, I32, I32, P, P, P]),
     "alto_mttkrp_ex": (I32, [P, I32, I32, I32, P, P, ctypes.POINTER(MttkrpPlan), P]),
     "alto_mttkrp_get_plan": (I32, [P, I32, I32, I32, ctypes.POINTER(MttkrpPlan)]),
+    "alto_mttkrp_noalloc": (I32, [P, I32, I32, I32, P, P, ctypes.POINTER(MttkrpPlan), P]),
     "alto_autotune": (I32, [P, I32, I32, I32, P, P, P, ctypes.POINTER(MttkrpPlan)]),
     "alto_mttkrp_batched": (I32, [I32, P, P, P, P, P, P, P]),
     "cpd_als_sweep": (I32, [P, I32, P, P, P]),

@@ -554,11 +554,66 @@ alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *
     return ALTO_OK;
 }
 
+// ---- allocation-free MTTKRP with FP64 accumulation (alto_mttkrp_noalloc)
+//
+// Its accumulation buffer is this file-scope device array, which every GPU
+// the library runs on holds until the process ends.  Host code never uses
+// the array's name as an address: once per device, with that device
+// current, its device address is looked up with hipGetSymbolAddress and kept;
+// kernels receive that address.  Calls that overlap on one GPU share the
+// array and race; every call clears what it uses first.
+constexpr uint64_t kScratchDoubles = uint64_t(1) << 23;  // 64 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64] = {};
+
+alto_status scratch_for(int dev, double **out) {
+    if (dev < 0 || dev >= 64) return fail(ALTO_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ALTO_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ALTO_OK;
+}
+}  // namespace
+
 }  // namespace alto
 
 using namespace alto;
 
 extern "C" {
+
+alto_status alto_mttkrp_noalloc(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors,
+                                float *out, const alto_mttkrp_plan *plan, void *stream) {
+    alto_status st = check_mttkrp_args(h, mode, rank, fdt, factors, out);
+    if (st != ALTO_OK) return st;
+    if (rank % 4) return fail(ALTO_ERR_ARG, "alto_mttkrp_noalloc: rank must be a multiple of 4");
+    if (plan && plan->accumulate != ALTO_ACC_DEFAULT && plan->accumulate != ALTO_ACC_F64)
+        return fail(ALTO_ERR_ARG, "alto_mttkrp_noalloc accumulates in FP64 only");
+    const uint64_t nout = h->info.dims[mode] * (uint64_t)rank;
+    if (nout > kScratchDoubles)
+        return fail(ALTO_ERR_ARG, "alto_mttkrp_noalloc: dims[mode] x rank = " + std::to_string(nout) +
+                                      " exceeds the static scratch of " + std::to_string(kScratchDoubles) +
+                                      " doubles");
+    int dev = -1;
+    ALTO_HIP(hipGetDevice(&dev));
+    if (dev != h->device) return fail(ALTO_ERR_ARG, "the handle's device is not the current device");
+    double *buf = nullptr;
+    st = scratch_for(dev, &buf);
+    if (st != ALTO_OK) return st;
+    alto_mttkrp_plan p;
+    st = resolve_plan(h, mode, rank, fdt, plan, &p);
+    if (st != ALTO_OK) return st;
+    p.accumulate = ALTO_ACC_F64;
+    return run_mttkrp(h, mode, rank, fdt, factors, out, p, (hipStream_t)stream, buf);
+}
 
 alto_status alto_mttkrp_ex(alto_handle h, int mode, int rank, alto_dtype fdt, const void *const *factors, float *out,
                            const alto_mttkrp_plan *plan, void *stream) {
