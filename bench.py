@@ -256,6 +256,7 @@ def phi_leg(T, X, facs, rank, words, ev):
         b_pi = X.nnz * (8 * words + (N - 1) * row + row)
         res["modes"].append({
             "mode": n, "otf_ms": round(otf_ms, 4), "pre_ms": round(pre_ms, 4), "pi_ms": round(pi_ms, 4),
+            "library_choice": "pre" if T.cpapr_prefer_pre(n, rank) else "otf",
             "otf_gbs": round(b_otf / otf_ms / 1e6, 1), "pre_gbs": round(b_pre / pre_ms / 1e6, 1),
             "pi_gbs": round(b_pi / pi_ms / 1e6, 1),
             "otf_frac": round(b_otf / otf_ms / 1e6 / HBM_PEAK_GBS, 4),
@@ -557,6 +558,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            # the same launch rated by its measured HBM-side bytes (counters)
+            "traffic_frac": round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
             "kernel": "k_mttkrp (main MTTKRP kernel), per MTTKRP (sum over its rank-tile launches), averaged over "
             "the timed region",
             "alg_bytes_per_launch": round(avg_bytes),

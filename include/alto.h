@@ -26,7 +26,11 @@
  *     host before anything is enqueued.
  *   - Limits: 1 <= nmodes <= ALTO_MAX_MODES; 1 <= dims[n] <= 2^31; the
  *     index width sum_n ceil(log2 dims[n]) <= 128 bits; nnz < 2^40;
- *     rank a multiple of 4 in 4..ALTO_MAX_RANK.
+ *     rank 1..ALTO_MAX_RANK for MTTKRP and 1..64 for the CP-ALS calls (the
+ *     R x R solve of a sweep runs in one workgroup's LDS).  A rank that is
+ *     not a multiple of 4 runs on zero-padded copies of the factors (rows of
+ *     the next multiple of 4) in handle workspace; the batched, serving and
+ *     CP-APR calls take multiples of 4 only.
  */
 #ifndef ALTO_MI355X_H
 #define ALTO_MI355X_H
@@ -102,7 +106,7 @@ typedef enum {
 typedef struct {
     int conflict;        /* alto_conflict                                          */
     int tile_nnz;        /* nonzeros per workgroup tile (line segment length)      */
-    int block_threads;   /* 256, 512 or 1024                                       */
+    int block_threads;   /* 256 or 512                                             */
     int table_slots;     /* LDS merge-table rows (power of two), TILE and HOT      */
     int accumulate;      /* alto_accumulate                                        */
     int rank_tile;       /* columns per pass (multiple of 4 dividing rank; 0: all) */
@@ -183,7 +187,12 @@ alto_status alto_decode(alto_handle h, uint64_t count, const uint64_t *keys, int
 alto_status alto_partition(alto_handle h, int64_t nseg, int64_t *starts_out, uint64_t *intervals_out,
                            void *stream);
 
-/* Release the handle and every buffer it owns (after its stream work). */
+/*
+ * Release the handle.  Its buffers return to the library's cache behind the
+ * work already enqueued on the last stream the handle was used with (an
+ * event recorded there; nothing waits).  Work the caller enqueued for the
+ * handle on other streams must have completed.
+ */
 alto_status alto_free(alto_handle h);
 
 /* ---------------------------------------------------------------- MTTKRP */
@@ -279,14 +288,25 @@ alto_status alto_cpapr_phi(alto_handle h, int mode, int rank, const float *const
  */
 alto_status alto_cpapr_pi(alto_handle h, int mode, int rank, const float *const *factors, float *pi, void *stream);
 
+/*
+ * The ALTO-PRE / ALTO-OTF choice for mode `mode` (Sec. "Adaptive Memory
+ * Management"): *pre (host) = 1 when the mode's fiber reuse nnz / dims[mode]
+ * is low (<= 4, the conflict-resolution rule's threshold) and the other
+ * factor matrices (rank columns, FP32) exceed twice the GPU's L2 over all
+ * XCDs (the GPU's fast memory), else 0.  Host only.
+ */
+alto_status alto_cpapr_prefer_pre(alto_handle h, int mode, int rank, int *pre /*host*/);
+
 /* ---------------------------------------------------------------- CP-ALS */
 
 /*
  * One CP-ALS sweep (Algorithm "alg:cp-als", one pass of the outer loop):
  * for n = 0..N-1: V = Hadamard product of the Grams A^(m)T A^(m), m != n
  * (FP64); M = MTTKRP(n); A^(n) = M V^-1 via an FP64 Cholesky factorisation of
- * V (symmetric-eigen pseudo-inverse when V is not positive definite, which
- * returns ALTO_ERR_NOT_SPD as a warning); lambda = column 2-norms of A^(n)
+ * V (symmetric-eigen pseudo-inverse when V is not positive definite; the call
+ * stays asynchronous, so it does not return ALTO_ERR_NOT_SPD: the fallback
+ * sets bit n of the flags alto_sweep_flags reads, and cpd_als returns the
+ * warning); lambda = column 2-norms of A^(n)
  * (FP64); columns of A^(n) divided by lambda (a zero column stays zero).
  * factors[m] (device FP32, dims[m] x rank) are updated in place; lambda
  * (device FP64 [rank]) receives the last mode's norms.  fdt = ALTO_BF16 makes
@@ -433,7 +453,8 @@ alto_status alto_serve_footprint(const alto_serve_job *job /*host*/, uint64_t *b
 alto_status alto_timing_enable(int on);
 alto_status alto_timing_read(uint64_t *launches /*host*/, double *total_ms /*host*/);
 
-/* Return every cached device block to the device (hipFree). */
+/* Return every cached device block to the device (hipFree).  Synchronizes
+ * the device first. */
 alto_status alto_release_cached_memory(void);
 
 /* ---------------------------------------------------------------- misc */

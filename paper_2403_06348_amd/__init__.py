@@ -226,6 +226,13 @@ class AltoTensor:
                                          _ptr(out), _stream(stream)), "alto_cpapr_pi")
         return out
 
+    def cpapr_prefer_pre(self, mode: int, rank: int) -> bool:
+        """The library's ALTO-PRE / ALTO-OTF choice for this mode and rank."""
+        v = ctypes.c_int()
+        _check(_capi.lib().alto_cpapr_prefer_pre(self.handle, int(mode), int(rank), ctypes.byref(v)),
+               "alto_cpapr_prefer_pre")
+        return bool(v.value)
+
     def cpapr_phi(self, mode: int, factors, B, eps=1e-10, pi=None, out=None, plan=None, stream=None):
         """CP-APR model update Phi of mode ``mode`` (pi: precomputed Pi rows
         from cpapr_pi for ALTO-PRE, else ALTO-OTF)."""

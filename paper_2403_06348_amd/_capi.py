@@ -151,6 +151,7 @@ SIGNATURES = {
     "alto_tensor_norm2": (I32, [P, ctypes.POINTER(ctypes.c_double), P]),
     "alto_cpapr_phi": (I32, [P, I32, I32, P, P, ctypes.c_float, P, P, ctypes.POINTER(MttkrpPlan), P]),
     "alto_cpapr_pi": (I32, [P, I32, I32, P, P, P]),
+    "alto_cpapr_prefer_pre": (I32, [P, I32, I32, ctypes.POINTER(I32)]),
     "alto_cp_fit": (I32, [P, I32, I32, P, P, ctypes.POINTER(ctypes.c_double), P]),
     "cpd_als": (I32, [P, I32, I32, P, P, I32, ctypes.c_double, P, ctypes.POINTER(I32), P]),
     "cpd_als_sweep_batched": (I32, [I32, P, P, P, P, P, P]),

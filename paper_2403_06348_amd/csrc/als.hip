@@ -634,8 +634,7 @@ alto_status upload_sweep_jobs(const std::vector<SweepJob> &host, hipStream_t s, 
     }
     if (st->cap < host.size()) {
         if (st->dev) {
-            ALTO_HIP(hipStreamSynchronize(s));
-            dev_free(st->dev);
+            dev_free_after(st->dev, s);
             st->dev = nullptr;
             st->cap = 0;
         }
@@ -654,6 +653,7 @@ alto_status upload_sweep_jobs(const std::vector<SweepJob> &host, hipStream_t s, 
 alto_status sweep_setup(alto_tensor *h, int rank, int fdt, float *const *factors, const double *lambda,
                         hipStream_t s) {
     ALTO_CHECK_HANDLE(h);
+    h->stream = s;
     const int N = h->info.nmodes;
     const int R = rank;
     if (R < 4 || R > kMaxSweepRank || R % 4) return fail(ALTO_ERR_ARG, "sweep rank must be in 1..64");
@@ -667,16 +667,16 @@ alto_status sweep_setup(alto_tensor *h, int rank, int fdt, float *const *factors
     for (int m = 0; m < N; m++) maxI = h->info.dims[m] > maxI ? h->info.dims[m] : maxI;
     const size_t rr = (size_t)R * R;
     const size_t need = (size_t)(N * rr + rr + (size_t)kPartials * rr + R) * 8;
-    alto_status st = ensure_ws(&h->ws_sweep, &h->ws_sweep_bytes, need);
+    alto_status st = ensure_ws(&h->ws_sweep, &h->ws_sweep_bytes, need, s);
     if (st != ALTO_OK) return st;
-    st = ensure_ws((void **)&h->ws_m, &h->ws_m_bytes, (size_t)maxI * R * 4);
+    st = ensure_ws((void **)&h->ws_m, &h->ws_m_bytes, (size_t)maxI * R * 4, s);
     if (st != ALTO_OK) return st;
     size_t flag_bytes = h->ws_flags ? 256 : 0;
-    st = ensure_ws((void **)&h->ws_flags, &flag_bytes, 256);
+    st = ensure_ws((void **)&h->ws_flags, &flag_bytes, 256, s);
     if (st != ALTO_OK) return st;
     if (fdt == ALTO_BF16) {
         for (int m = 0; m < N; m++) {
-            st = ensure_ws((void **)&h->ws_bf16[m], &h->ws_bf16_bytes[m], (size_t)h->info.dims[m] * R * 2);
+            st = ensure_ws((void **)&h->ws_bf16[m], &h->ws_bf16_bytes[m], (size_t)h->info.dims[m] * R * 2, s);
             if (st != ALTO_OK) return st;
         }
     }
@@ -787,7 +787,7 @@ alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *con
     void *pf[ALTO_MAX_MODES];
     alto_status st = pad_factors(h, rank, ALTO_F32, (const void *const *)factors, -1, pf, s);
     if (st != ALTO_OK) return st;
-    st = ensure_ws((void **)&h->ws_lampad, &h->ws_lampad_bytes, (size_t)R4 * sizeof(double));
+    st = ensure_ws((void **)&h->ws_lampad, &h->ws_lampad_bytes, (size_t)R4 * sizeof(double), s);
     if (st != ALTO_OK) return st;
     st = sweep_run(h, R4, rank, fdt, (float *const *)pf, h->ws_lampad, s);
     if (st != ALTO_OK) return st;

@@ -80,6 +80,7 @@ struct alto_tensor {
     int device;
     alto_info_t info;
     alto::LinePlan lp;
+    hipStream_t stream;  // stream of the last call that enqueued work for the handle
     uint64_t *keys;  // nnz * words, ordered by ALTO index
     float *vals;     // nnz
     // workspace (grown on demand)

@@ -46,6 +46,7 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
     for (int k = 0; k < nj; k++) {
         const int j = g.items[k];
         alto_tensor *h = hs[j];
+        h->stream = s;
         alto_mttkrp_plan p = default_plan(h, modes[j], ranks[j], g.fdt);
         p.conflict = ALTO_CR_TILE;
         p.rank_tile = 0;
@@ -74,8 +75,7 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
     }
     if (st->bytes < need) {
         if (st->dev) {
-            ALTO_HIP(hipStreamSynchronize(s));
-            dev_free(st->dev);
+            dev_free_after(st->dev, s);
             st->dev = nullptr;
             st->bytes = 0;
         }
@@ -212,7 +212,7 @@ alto_status alto_autotune(alto_handle h, int mode, int rank, alto_dtype fdt, con
     void *pf[ALTO_MAX_MODES];
     st = pad_factors(h, rank, fdt, factors, mode, pf, s);
     if (st != ALTO_OK) return st;
-    st = ensure_ws((void **)&h->ws_pad_out, &h->ws_pad_out_bytes, h->info.dims[mode] * (size_t)R4 * 4);
+    st = ensure_ws((void **)&h->ws_pad_out, &h->ws_pad_out_bytes, h->info.dims[mode] * (size_t)R4 * 4, s);
     if (st != ALTO_OK) return st;
     st = autotune_run(h, mode, R4, fdt, (const void *const *)pf, h->ws_pad_out, s, chosen);
     if (st != ALTO_OK) return st;

@@ -453,6 +453,7 @@ alto_status alto_build(int nmodes, const uint64_t *dims, uint64_t nnz, const int
     memset(h, 0, sizeof(*h));
     h->magic = kHandleMagic;
     ALTO_HIP(hipGetDevice(&h->device));
+    h->stream = s;
     info.nnz = nnz;
     h->info = info;
     h->lp = lp;
@@ -546,6 +547,7 @@ alto_status alto_info(alto_handle h, alto_info_t *out) {
 alto_status alto_export(alto_handle h, uint64_t *keys_out, float *vals_out, void *stream) {
     ALTO_CHECK_HANDLE(h);
     hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
     const uint64_t n = h->info.nnz;
     if (n == 0) return ALTO_OK;
     if (keys_out)
@@ -559,6 +561,7 @@ alto_status alto_decode(alto_handle h, uint64_t count, const uint64_t *keys, int
     if (count == 0) return ALTO_OK;
     if (!keys || !coords_out) return fail(ALTO_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
     const unsigned grid = grid_for(count, 256, 8192);
     if (h->info.index_words == 2) hipLaunchKernelGGL(k_decode<2>, dim3(grid), dim3(256), 0, s, h->lp, keys, count, coords_out);
     else hipLaunchKernelGGL(k_decode<1>, dim3(grid), dim3(256), 0, s, h->lp, keys, count, coords_out);
@@ -571,6 +574,7 @@ alto_status alto_partition(alto_handle h, int64_t nseg, int64_t *starts_out, uin
     if (nseg < 1 || (uint64_t)nseg > (uint64_t(1) << 32)) return fail(ALTO_ERR_ARG, "nseg must be in 1..2^32");
     if (!starts_out || !intervals_out) return fail(ALTO_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
     const unsigned grid = (unsigned)std::min<int64_t>(nseg, 65536);
     if (h->info.index_words == 2)
         hipLaunchKernelGGL(k_partition<2>, dim3(grid), dim3(256), 0, s, h->lp, h->keys, h->info.nnz, (uint64_t)nseg,
@@ -584,19 +588,20 @@ alto_status alto_partition(alto_handle h, int64_t nseg, int64_t *starts_out, uin
 
 alto_status alto_free(alto_handle h) {
     ALTO_CHECK_HANDLE(h);
-    // buffers go back to the cache: wait for any work that may still use them
-    (void)hipDeviceSynchronize();
-    dev_free(h->keys);
-    dev_free(h->vals);
-    dev_free(h->ws_acc);
-    dev_free(h->ws_sweep);
-    dev_free(h->ws_m);
-    dev_free(h->ws_flags);
-    dev_free(h->ws_fit);
-    dev_free(h->ws_pad_out);
-    dev_free(h->ws_lampad);
-    for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free(h->ws_pad[n]);
-    for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free(h->ws_bf16[n]);
+    // buffers go back to the cache behind the work already enqueued on the
+    // handle's last stream; nothing waits here
+    const hipStream_t s = h->stream;
+    dev_free_after(h->keys, s);
+    dev_free_after(h->vals, s);
+    dev_free_after(h->ws_acc, s);
+    dev_free_after(h->ws_sweep, s);
+    dev_free_after(h->ws_m, s);
+    dev_free_after(h->ws_flags, s);
+    dev_free_after(h->ws_fit, s);
+    dev_free_after(h->ws_pad_out, s);
+    dev_free_after(h->ws_lampad, s);
+    for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free_after(h->ws_pad[n], s);
+    for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free_after(h->ws_bf16[n], s);
     h->magic = 0;
     delete h;
     return ALTO_OK;

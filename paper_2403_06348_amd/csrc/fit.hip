@@ -263,8 +263,9 @@ constexpr int kFitSlots = 2;  // ws_fit: [0] = ||X||^2, [1] = last fit
 
 // ||X||^2 of the handle's tensor into h->ws_fit[0], once per handle.
 alto_status ensure_xnorm2(alto_tensor *h, hipStream_t s) {
+    h->stream = s;
     size_t have = h->ws_fit_bytes;
-    alto_status st = ensure_ws((void **)&h->ws_fit, &have, kFitSlots * sizeof(double));
+    alto_status st = ensure_ws((void **)&h->ws_fit, &have, kFitSlots * sizeof(double), s);
     if (st != ALTO_OK) return st;
     h->ws_fit_bytes = have;
     if (h->xnorm_ready) return ALTO_OK;
@@ -332,7 +333,7 @@ alto_status alto_cp_fit(alto_handle h, int rank, alto_dtype fdt, float *const *f
         const int R4 = padded_rank(rank);
         st = pad_factors(h, rank, ALTO_F32, (const void *const *)factors, -1, pf, s);
         if (st != ALTO_OK) return st;
-        st = ensure_ws((void **)&h->ws_lampad, &h->ws_lampad_bytes, (size_t)R4 * sizeof(double));
+        st = ensure_ws((void **)&h->ws_lampad, &h->ws_lampad_bytes, (size_t)R4 * sizeof(double), s);
         if (st != ALTO_OK) return st;
         hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, s, h->ws_lampad, (uint64_t)R4, 0.0);
         ALTO_HIP(hipMemcpyAsync(h->ws_lampad, lambda, (size_t)rank * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -390,7 +391,7 @@ alto_status cpd_als(alto_handle h, int rank, alto_dtype fdt, float *const *facto
     if (R4 != rank) {
         alto_status st = pad_factors(h, rank, ALTO_F32, (const void *const *)factors, -1, pf, s);
         if (st != ALTO_OK) return st;
-        st = ensure_ws((void **)&h->ws_lampad, &h->ws_lampad_bytes, (size_t)R4 * sizeof(double));
+        st = ensure_ws((void **)&h->ws_lampad, &h->ws_lampad_bytes, (size_t)R4 * sizeof(double), s);
         if (st != ALTO_OK) return st;
         F = (float *const *)pf;
         lam = h->ws_lampad;

@@ -56,7 +56,9 @@ void accuracy_policy(const alto_tensor *h, int mode, int rank, alto_mttkrp_plan 
 constexpr uint64_t kBatchF32MaxTiles = 2048;  // batched launches: tiles per job at most
 alto_status check_mttkrp_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
                               const float *out);
-alto_status ensure_ws(void **p, size_t *have, size_t need);
+// Grow a workspace buffer to `need` bytes; a replaced buffer is released
+// behind the work already enqueued on s (no synchronization).
+alto_status ensure_ws(void **p, size_t *have, size_t need, hipStream_t s);
 // acc_buf: accumulation buffer for FP64 / per-XCD plans (NULL: handle workspace)
 alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
                        const alto_mttkrp_plan &p, hipStream_t s, void *acc_buf = nullptr);
@@ -88,6 +90,7 @@ alto_status check_launch_lds(const void *kern, size_t dyn, int dev);
 const void *zero_outputs_kernel();
 int device_cus(int dev);
 size_t device_lds(int dev);  // LDS bytes one workgroup may allocate
+size_t device_cache_bytes(int dev);  // L2 bytes over all XCDs
 
 // batched MTTKRP (batch.hip), arguments already validated
 alto_status batched_run(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,

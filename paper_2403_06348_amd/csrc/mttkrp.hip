@@ -30,10 +30,10 @@ const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch) {
 }
 
 // The specialised kernel serves 3-mode tensors with a one-word index whose
-// factor reads fit 32-bit offsets and whose updates go straight to the FP32
-// output; everything else takes the general kernel.
+// factor reads fit 32-bit offsets and whose updates are FP32 additions (into
+// the output or its per-XCD copies); everything else takes the general kernel.
 const void *pick_single(int lpn, int fdt, int words, const MttkrpArgs &a) {
-    if (words == 1 && a.nmodes == 3 && a.buf32 && !a.use64 && a.copies == 1)
+    if (words == 1 && a.nmodes == 3 && a.buf32 && !a.use64)
         return fdt == ALTO_BF16 ? pick_fast_bf16(lpn, a.tile_merge) : pick_fast_f32(lpn, a.tile_merge);
     return pick_kernel(lpn, fdt, words, a.nmodes, false);
 }
@@ -44,7 +44,8 @@ namespace {
 
 struct DevProps {
     int cus = 0;
-    size_t lds = 0;  // LDS bytes one workgroup may allocate
+    size_t lds = 0;    // LDS bytes one workgroup may allocate
+    size_t cache = 0;  // L2 bytes over all XCDs
 };
 
 DevProps &props(int dev);
@@ -52,6 +53,7 @@ DevProps &props(int dev);
 
 int device_cus(int dev) { return props(dev).cus; }
 size_t device_lds(int dev) { return props(dev).lds; }
+size_t device_cache_bytes(int dev) { return props(dev).cache; }
 
 // Static LDS of the MTTKRP kernels (extraction masks, counters) is below
 // this; plans budget it beside their tables and record staging.
@@ -101,9 +103,12 @@ DevProps &props(int dev) {
         if (hipGetDeviceProperties(&dp, dev) == hipSuccess) {
             p[dev].cus = dp.multiProcessorCount;
             p[dev].lds = dp.sharedMemPerBlock;
+            // the runtime reports one XCD's L2
+            p[dev].cache = (size_t)dp.l2CacheSize * kXcdCopies;
         } else {
             p[dev].cus = 256;
             p[dev].lds = 64 * 1024;
+            p[dev].cache = size_t(32) << 20;
         }
     }
     return p[dev < 0 || dev >= 64 ? 0 : dev];
@@ -337,7 +342,7 @@ alto_status pad_factors(alto_tensor *h, int rank, int fdt, const void *const *fa
         fptr[m] = nullptr;
         if (m == skip) continue;
         if (!factors[m]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(m) + "] is NULL");
-        alto_status st = ensure_ws(&h->ws_pad[m], &h->ws_pad_bytes[m], h->info.dims[m] * (size_t)R4 * es);
+        alto_status st = ensure_ws(&h->ws_pad[m], &h->ws_pad_bytes[m], h->info.dims[m] * (size_t)R4 * es, s);
         if (st != ALTO_OK) return st;
         launch_copy_cols(factors[m], rank, h->ws_pad[m], R4, h->info.dims[m], es, s);
         fptr[m] = h->ws_pad[m];
@@ -346,11 +351,11 @@ alto_status pad_factors(alto_tensor *h, int rank, int fdt, const void *const *fa
     return ALTO_OK;
 }
 
-alto_status ensure_ws(void **p, size_t *have, size_t need) {
+alto_status ensure_ws(void **p, size_t *have, size_t need, hipStream_t s) {
     if (*have >= need && *p) return ALTO_OK;
     if (*p) {
-        ALTO_HIP(hipDeviceSynchronize());
-        dev_free(*p);
+        // the old buffer returns to the cache behind the work already on s
+        dev_free_after(*p, s);
         *p = nullptr;
         *have = 0;
     }
@@ -508,6 +513,7 @@ alto_status launch_stretch_kernel(const alto_tensor *h, const void *kern, const 
 
 alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *const *factors, float *out,
                        const alto_mttkrp_plan &p, hipStream_t s, void *acc_buf) {
+    h->stream = s;
     const uint64_t nout = h->info.dims[mode] * (uint64_t)rank;
     const bool f64 = p.accumulate == ALTO_ACC_F64 || p.accumulate == ALTO_ACC_XCD_F64;
     const int copies = (p.accumulate == ALTO_ACC_XCD_F32 || p.accumulate == ALTO_ACC_XCD_F64) ? kXcdCopies : 1;
@@ -520,7 +526,7 @@ alto_status run_mttkrp(alto_tensor *h, int mode, int rank, int fdt, const void *
         // handle workspace
         void *buf = acc_buf;
         if (!buf) {
-            alto_status st = ensure_ws(&h->ws_acc, &h->ws_acc_bytes, nout * copies * (f64 ? 8 : 4));
+            alto_status st = ensure_ws(&h->ws_acc, &h->ws_acc_bytes, nout * copies * (f64 ? 8 : 4), s);
             if (st != ALTO_OK) return st;
             buf = h->ws_acc;
         }
@@ -633,7 +639,7 @@ alto_status alto_mttkrp_ex(alto_handle h, int mode, int rank, alto_dtype fdt, co
     void *pf[ALTO_MAX_MODES];
     st = pad_factors(h, rank, fdt, factors, mode, pf, s);
     if (st != ALTO_OK) return st;
-    st = ensure_ws((void **)&h->ws_pad_out, &h->ws_pad_out_bytes, h->info.dims[mode] * (size_t)R4 * 4);
+    st = ensure_ws((void **)&h->ws_pad_out, &h->ws_pad_out_bytes, h->info.dims[mode] * (size_t)R4 * 4, s);
     if (st != ALTO_OK) return st;
     st = run_mttkrp(h, mode, R4, fdt, (const void *const *)pf, h->ws_pad_out, p, s);
     if (st != ALTO_OK) return st;

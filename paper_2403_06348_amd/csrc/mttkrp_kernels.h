@@ -93,11 +93,12 @@ __device__ inline uint32_t xcd_id() { return __builtin_amdgcn_s_getreg(20 | (0 <
 
 // Add 4 columns of partial sums (FP32 run sums or FP64 LDS rows) to the
 // output row, or to this XCD's copy of it.
-// FAST: the plan is known to add FP32 straight into the output.
+// FAST: the plan is known to add FP32 into the output or its per-XCD copies.
 template <bool FAST = false, typename T>
 __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, const T *acc) {
     uint64_t o = (uint64_t)row * a.ld + a.col0 + r0;
     if (FAST) {
+        if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
 #pragma unroll
         for (int j = 0; j < 4; j++)
             if (r0 + j < a.rank) unsafeAtomicAdd(a.out32 + o + j, (float)acc[j]);

@@ -78,6 +78,7 @@ alto_mttkrp_plan phi_plan(const alto_tensor *h, int mode, int rank, const alto_m
 
 alto_status run_phi(alto_tensor *h, int mode, int rank, const void *const *factors, const float *B, float eps,
                     const float *pi, float *phi, const alto_mttkrp_plan *in, hipStream_t s) {
+    h->stream = s;
     int tw = 2;
     const alto_mttkrp_plan p = phi_plan(h, mode, rank, in, &tw);
     const uint64_t nout = h->info.dims[mode] * (uint64_t)rank;
@@ -85,7 +86,7 @@ alto_status run_phi(alto_tensor *h, int mode, int rank, const void *const *facto
     double *out64 = nullptr;
     const unsigned g = grid_for(nout, 256, 16384);
     if (f64) {
-        alto_status st = ensure_ws(&h->ws_acc, &h->ws_acc_bytes, nout * 8);
+        alto_status st = ensure_ws(&h->ws_acc, &h->ws_acc_bytes, nout * 8, s);
         if (st != ALTO_OK) return st;
         out64 = (double *)h->ws_acc;
         hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, s, out64, nout, 0.0);
@@ -126,6 +127,7 @@ alto_status alto_cpapr_pi(alto_handle h, int mode, int rank, const float *const 
     if (!pi || ((uintptr_t)pi & 15)) return fail(ALTO_ERR_ARG, "pi must be a 16-byte aligned device pointer");
     if (h->info.nnz == 0) return ALTO_OK;
     hipStream_t s = (hipStream_t)stream;
+    h->stream = s;
     alto_mttkrp_plan p;
     memset(&p, 0, sizeof(p));
     p.conflict = ALTO_CR_RUN;
@@ -139,6 +141,21 @@ alto_status alto_cpapr_pi(alto_handle h, int mode, int rank, const float *const 
     const unsigned grid = grid_for(h->info.nnz * (uint64_t)lpn, 256, 16384);
     void *args[] = {(void *)&a, (void *)&pi};
     ALTO_HIP(hipLaunchKernel(kern, dim3(grid), dim3(256), args, 0, s));
+    return ALTO_OK;
+}
+
+alto_status alto_cpapr_prefer_pre(alto_handle h, int mode, int rank, int *pre) {
+    ALTO_CHECK_HANDLE(h);
+    if (!pre) return fail(ALTO_ERR_ARG, "pre is NULL");
+    if (mode < 0 || mode >= h->info.nmodes) return fail(ALTO_ERR_ARG, "mode out of range");
+    if (rank < 1) return fail(ALTO_ERR_ARG, "rank must be positive");
+    // low fiber reuse (the conflict-resolution rule's threshold) and factor
+    // matrices of the other modes well beyond the on-chip cache
+    const double reuse = (double)h->info.nnz / (double)h->info.dims[mode];
+    uint64_t fbytes = 0;
+    for (int m = 0; m < h->info.nmodes; m++)
+        if (m != mode) fbytes += h->info.dims[m] * (uint64_t)rank * 4;
+    *pre = (reuse <= 4.0 && fbytes > 2 * device_cache_bytes(h->device)) ? 1 : 0;
     return ALTO_OK;
 }
 

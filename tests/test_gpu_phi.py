@@ -98,3 +98,14 @@ def test_phi_argument_errors():
         T.cpapr_phi(0, gf, torch.rand(X.dims[0], 6, device="cuda"))
     with pytest.raises(alto.AltoError):
         T.cpapr_phi(0, None, B)  # OTF needs the factors
+
+
+def test_pre_otf_choice():
+    """ALTO-PRE is chosen for low fiber reuse with factors far beyond the
+    GPU's L2; ALTO-OTF otherwise (Sec. "Adaptive Memory Management")."""
+    X, T = built("lowreuse")  # 3e6 x 2e6 x 4e6, 4e5 nonzeros: reuse < 1
+    assert T.cpapr_prefer_pre(0, 16)
+    X2, T2 = built("c2s")  # reuse 1.2 .. 12 with factors of 1e5 .. 1e6 rows
+    assert not T2.cpapr_prefer_pre(2, 16)  # reuse 12
+    X3, T3 = built("c1")
+    assert not any(T3.cpapr_prefer_pre(n, 8) for n in range(3))  # factors fit in L2
