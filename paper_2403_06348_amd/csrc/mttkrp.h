@@ -66,6 +66,7 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
                const alto_mttkrp_plan &p, float *out32, double *out64, MttkrpArgs *a, int col0 = 0,
                int rank_tile = 0);
 size_t lds_bytes(const MttkrpArgs &a, int threads);
+size_t outbox_bytes(int rank, int threads);  // per-wave outboxes of a launch
 int lpn_for(int rank);
 int pow2_floor(int v);
 alto_status launch_mttkrp(const alto_tensor *h, int fdt, const MttkrpArgs &a, int threads, hipStream_t s);

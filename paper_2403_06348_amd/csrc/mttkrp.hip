@@ -67,9 +67,17 @@ int record_words(int nmodes, int words) {
     return (nmodes + 1 + 3) / 4 * 4;
 }
 
+// The per-wave outboxes of rows bound for the output (see the kernels):
+// two slots per lane group, each a row index and `rank` FP32 columns.
+size_t outbox_bytes(int rank, int threads) {
+    const int cap = 2 * (64 / lpn_for(rank));
+    return (size_t)(threads / 64) * cap * (rank + 1) * 4;
+}
+
 size_t tile_plan_lds(const alto_tensor *h, int rank_tile, int slots, int threads) {
     const size_t rec = (size_t)record_words(h->info.nmodes, h->info.index_words);
-    return (size_t)slots * (2 * (rank_tile + 1) + 2) * 4 + (size_t)threads * rec * 4 + kStaticLdsAllowance;
+    return (size_t)slots * (2 * (rank_tile + 1) + 2) * 4 + (size_t)threads * rec * 4 + outbox_bytes(rank_tile, threads) +
+           kStaticLdsAllowance;
 }
 
 bool tile_plan_fits(const alto_tensor *h, int rank_tile, int slots, int threads) {
@@ -420,7 +428,9 @@ size_t lds_bytes(const MttkrpArgs &a, int threads) {
     const size_t S = hashed ? ((size_t)1 << a.slots_log2) : (a.tile_merge == 2 ? a.dim_out : 0);
     const size_t SK = hashed ? S : 0;
     const size_t TW = a.tile_merge == 2 ? (size_t)a.tw : 2;  // words per table element
-    return ((2 * SK + TW * S * (a.rank + 1) + 3) & ~(size_t)3) * 4 + (size_t)threads * a.rec * 4;
+    // the whole-mode table needs no outbox: all its rows are in LDS
+    const size_t ob = a.tile_merge == 2 ? 0 : outbox_bytes(a.rank, threads);
+    return ((2 * SK + TW * S * (a.rank + 1) + 3) & ~(size_t)3) * 4 + (size_t)threads * a.rec * 4 + ob;
 }
 
 // ---- optional per-launch timing with HIP events

@@ -116,6 +116,26 @@ __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, con
     }
 }
 
+// Add one column of a partial row (FP64 LDS rows or FP32 run sums) to the
+// output row, or to this XCD's copy of it.  The table flushes call it with
+// consecutive threads on consecutive columns of a row, so that one atomic
+// instruction covers up to 16 columns (64 bytes) of a row: the L2 takes one
+// request per instruction and row segment, and 4-column pieces per lane
+// would cost four requests for the same 64 bytes.
+template <bool FAST = false, typename T>
+__device__ inline void global_add1(const MttkrpArgs &a, uint32_t row, int c, T v) {
+    uint64_t o = (uint64_t)row * a.ld + a.col0 + c;
+    if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
+    if (!FAST && a.use64) unsafeAtomicAdd(a.out64 + o, (double)v);
+    else unsafeAtomicAdd(a.out32 + o, (float)v);
+}
+
+// (slot, column) of flat element i of a table of rows with `rank` columns.
+__device__ inline void split_elem(int i, int rank, int sh, int *slot, int *c) {
+    *slot = sh >= 0 ? (i >> sh) : i / rank;
+    *c = i - *slot * rank;
+}
+
 // Slot of `row` in the LDS table of partial rows, inserting it if absent.
 // The table is bucketized: a row lives in one of the 4 slots of its bucket,
 // read with a single 16-byte LDS load; an absent row takes the first empty
@@ -211,6 +231,81 @@ __device__ inline void flush_run(const MttkrpArgs &a, void *tval, uint32_t *thit
 
 constexpr uint32_t kFlushMark = 0xFFFFFFFFu;
 
+// ---- per-wave outbox of merged rows bound for the output
+//
+// A group (LPN lanes, 4 columns each) that flushes a run straight to the
+// output would issue 4 atomic instructions per row, each covering 4 lanes:
+// the L2 takes one request per instruction and 64-byte row segment, so a
+// 16-column row costs 4 requests.  Instead the group appends the row to its
+// wave's outbox in LDS, and the wave later adds whole rows with consecutive
+// lanes on consecutive columns (one request per 64-byte segment).  Slots are
+// assigned by a ballot over the groups that flush in the same instruction;
+// the count lives in LDS (one word per wave) so that lanes that left a loop
+// early and rejoin see it.  A full outbox falls back to direct atomics.
+struct Outbox {
+    uint32_t *rows;   // cap row indices
+    float *vals;      // cap x rank columns
+    uint32_t *count;  // entries in use (this wave's word)
+    int cap;
+};
+
+// Outbox slots per wave for `lpn` lanes per group: two per group, so that a
+// drain after every record (at most one entry per group) never overflows.
+__host__ __device__ inline int outbox_cap(int lpn) { return 2 * (64 / lpn); }
+
+__device__ inline Outbox outbox_of(uint32_t *obase, uint32_t *counts, int rank, int lpn) {
+    const int cap = outbox_cap(lpn);
+    const int w = threadIdx.x >> 6;
+    uint32_t *p = obase + (size_t)w * cap * (rank + 1);
+    return Outbox{p, (float *)(p + cap), counts + w, cap};
+}
+
+// Add every row of the outbox to the output, the wave's active lanes taking
+// consecutive columns; empties the outbox.
+template <bool FAST>
+__device__ inline void ob_drain(const Outbox &ob, const MttkrpArgs &a) {
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t n = *ob.count;
+    if (n == 0) return;
+    const uint64_t act = __activemask();
+    const int me = __popcll(act & ((uint64_t(1) << (threadIdx.x & 63)) - 1));
+    const int na = __popcll(act);
+    const int rk = a.rank;
+    const int sh = (rk & (rk - 1)) == 0 ? __ffs(rk) - 1 : -1;
+    for (int i = me; i < (int)n * rk; i += na) {
+        int e, c;
+        split_elem(i, rk, sh, &e, &c);
+        global_add1<FAST>(a, ob.rows[e], c, ob.vals[e * rk + c]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    *ob.count = 0u;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Groups with `want` set (uniform inside a group) append row `row` (lane q
+// holds columns r0..r0+3 in acc) to the outbox.
+template <bool FAST>
+__device__ inline void ob_put(const Outbox &ob, const MttkrpArgs &a, bool want, uint32_t row, int q, int r0,
+                              const float *acc) {
+    const uint64_t bal = __ballot(want && q == 0);
+    if (bal == 0) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = *ob.count;
+    const int pos = (int)n + __popcll(bal & ((uint64_t(1) << (lane - q)) - 1));
+    if (want) {
+        if (pos < ob.cap) {
+            if (q == 0) ob.rows[pos] = row;
+            if (r0 < a.rank) *(float4 *)(ob.vals + (size_t)pos * a.rank + r0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        } else {
+            global_add<FAST>(a, row, r0, acc);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t nn = min((uint32_t)ob.cap, n + (uint32_t)__popcll(bal));
+    *ob.count = nn;
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Coordinate k of the other modes from a staged record held as two uint4.
 __device__ inline uint32_t rec_coord(const uint4 &h, const uint4 &h2, int k) {
     return k == 0 ? h.z : k == 1 ? h.w : k == 2 ? h2.x : k == 3 ? h2.y : k == 4 ? h2.z : h2.w;
@@ -229,37 +324,35 @@ __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int 
     const int tid = threadIdx.x;
     double *tv64 = (double *)tval;
     float *tv32 = (float *)tval;
+    // one column per thread (see global_add1); sh: log2(rank), or -1
+    const int rk = a.rank;
+    const int sh = (rk & (rk - 1)) == 0 ? __ffs(rk) - 1 : -1;
     if (TM == 2 && t + 1 == t1) {
         // ---- end of the stretch: every row of the mode held in LDS is
         // added to the output once
         __syncthreads();
-        const int qr = a.rank >> 2;
-        for (int i = tid; i < S * qr; i += blockDim.x) {
-            const int row = i / qr, part = i - row * qr;
+        for (int i = tid; i < S * rk; i += blockDim.x) {
+            int row, c;
+            split_elem(i, rk, sh, &row, &c);
             if (TW == 2) {
-                const double *tv = tv64 + (size_t)row * TS + part * 4;
-                const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                if (vv[0] != 0.0 || vv[1] != 0.0 || vv[2] != 0.0 || vv[3] != 0.0)
-                    global_add<FAST>(a, (uint32_t)row, part * 4, vv);
+                const double v = tv64[(size_t)row * TS + c];
+                if (v != 0.0) global_add1<FAST>(a, (uint32_t)row, c, v);
             } else {
-                const float *tv = tv32 + (size_t)row * TS + part * 4;
-                const float vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                if (vv[0] != 0.f || vv[1] != 0.f || vv[2] != 0.f || vv[3] != 0.f)
-                    global_add<FAST>(a, (uint32_t)row, part * 4, vv);
+                const float v = tv32[(size_t)row * TS + c];
+                if (v != 0.f) global_add1<FAST>(a, (uint32_t)row, c, v);
             }
         }
         __syncthreads();
     } else if (TM == 3 && t + 1 == t1) {
         // ---- end of the stretch: the hot rows' partial sums go to the output
         __syncthreads();
-        const int qr = a.rank >> 2;
-        for (int i = tid; i < S * qr; i += blockDim.x) {
-            const int slot = i / qr, part = i - slot * qr;
+        for (int i = tid; i < S * rk; i += blockDim.x) {
+            int slot, c;
+            split_elem(i, rk, sh, &slot, &c);
             const uint32_t row = tkey[slot];
             if (row == kEmptyRow) continue;
-            const double *tv = tv64 + (size_t)slot * TS + part * 4;
-            const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-            if (vv[0] != 0.0 || vv[1] != 0.0 || vv[2] != 0.0 || vv[3] != 0.0) global_add<FAST>(a, row, part * 4, vv);
+            const double v = tv64[(size_t)slot * TS + c];
+            if (v != 0.0) global_add1<FAST>(a, row, c, v);
         }
         __syncthreads();
     } else if (TM == 1) {
@@ -274,17 +367,13 @@ __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int 
             thits[i] = keep ? 0u : kFlushMark;
         }
         __syncthreads();
-        const int qr = a.rank >> 2;
-        for (int i = tid; i < S * qr; i += blockDim.x) {
-            const int slot = i / qr, part = i - slot * qr;
+        for (int i = tid; i < S * rk; i += blockDim.x) {
+            int slot, c;
+            split_elem(i, rk, sh, &slot, &c);
             if (thits[slot] == kFlushMark) {
-                double *tv = tv64 + (size_t)slot * TS + part * 4;
-                const double vv[4] = {tv[0], tv[1], tv[2], tv[3]};
-                global_add<FAST>(a, tkey[slot], part * 4, vv);
-                tv[0] = 0.0;
-                tv[1] = 0.0;
-                tv[2] = 0.0;
-                tv[3] = 0.0;
+                double *tv = tv64 + (size_t)slot * TS + c;
+                global_add1<FAST>(a, tkey[slot], c, *tv);
+                *tv = 0.0;
             }
         }
         __syncthreads();
@@ -720,6 +809,12 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
     const int r0 = 4 * q;
     const bool ract = r0 < a.rank;
     const bool buf32 = FAST || a.buf32;
+    // the outbox follows the record staging (none for the whole-mode table,
+    // whose rows are all in LDS)
+    __shared__ uint32_t ob_counts[16];
+    if ((tid & 63) == 0) ob_counts[tid >> 6] = 0u;
+    const Outbox ob = outbox_of(stage + (size_t)ngrp * LPN * RW, ob_counts, a.rank, LPN);
+    constexpr int kGroupsPerWave = 64 / LPN;
     __amdgpu_buffer_rsrc_t rs[MAXO];
 #pragma unroll
     for (int k = 0; k < MAXO; k++)
@@ -849,12 +944,13 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
                 }
             }
         };
-        // products of a step, merged into runs of equal destinations
+        // products of a step, merged into runs of equal destinations; a
+        // finished run goes to its LDS slot, or to the wave's outbox
         auto consume = [&](const float4 (&g)[MAXO][SB], const uint32_t (&dv)[SB], const float (&vv)[SB],
                            const float4 (&gB)[SB]) {
 #pragma unroll
             for (int s = 0; s < SB; s++) {
-                if (dv[s] == kEmptyRow) continue;
+                const bool live = dv[s] != kEmptyRow;
                 const float v0 = OP == kOpMttkrp ? vv[s] : 1.f;
                 float p[4] = {v0, v0, v0, v0};
 #pragma unroll
@@ -875,15 +971,19 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
 #pragma unroll
                     for (int j = 0; j < 4; j++) p[j] *= sc;
                 }
-                if (dv[s] == cur) {
+                const bool same = live && dv[s] == cur;
+                const bool fl = live && !same && cur != kEmptyRow;
+                ob_put<FAST>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc);
+                if (fl && (cur & kSlotBit)) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
+                if (same) {
 #pragma unroll
                     for (int j = 0; j < 4; j++) acc[j] += p[j];
-                } else {
-                    if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
+                } else if (live) {
                     cur = dv[s];
 #pragma unroll
                     for (int j = 0; j < 4; j++) acc[j] = p[j];
                 }
+                if (*ob.count > (uint32_t)(ob.cap - kGroupsPerWave)) ob_drain<FAST>(ob, a);
             }
         };
 
@@ -899,7 +999,12 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
             if (k + 2 < nsteps) issue(k + 2, xg, xd, xv, xb);
             consume(yg, yd, yv, yb);
         }
-        if (cur != kEmptyRow) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
+        {
+            const bool fl = cur != kEmptyRow;
+            ob_put<FAST>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc);
+            if (fl && (cur & kSlotBit)) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
+        }
+        ob_drain<FAST>(ob, a);
         __builtin_amdgcn_wave_barrier();
         tile_end<FAST>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
     }

@@ -44,7 +44,8 @@ size_t phi_lds(const alto_tensor *h, int mode, int rank, const alto_mttkrp_plan 
     size_t table = 0;
     if (p.conflict == ALTO_CR_TILE) table = (size_t)p.table_slots * (2 * (rank + 1) + 2) * 4;
     else if (p.conflict == ALTO_CR_DIRECT) table = (size_t)h->info.dims[mode] * (rank + 1) * 4 * tw;
-    return table + (size_t)p.block_threads * kPhiRec * 4 + static_lds_allowance();
+    const size_t ob = p.conflict == ALTO_CR_DIRECT ? 0 : outbox_bytes(rank, p.block_threads);
+    return table + (size_t)p.block_threads * kPhiRec * 4 + ob + static_lds_allowance();
 }
 
 // The MTTKRP plan of the mode, adapted to the Phi kernels: full rank in one

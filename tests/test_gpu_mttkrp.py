@@ -204,18 +204,23 @@ def test_mttkrp_whole_mode_lds_and_rank_tiles(name, rank, mode, plan):
 
 
 def test_plans_beyond_the_lds_are_rejected():
-    """A hashed-table plan whose table, record staging and static LDS exceed
-    the 160 KiB a workgroup may hold is refused before any launch; the
-    largest one that fits runs and matches the oracle."""
+    """A hashed-table plan whose table, record staging, outboxes and static
+    LDS exceed the 160 KiB a workgroup may hold is refused before any
+    launch; the largest one that fits runs and matches the oracle."""
     X, T = built("c2s")
     g32 = [torch.rand(d, 32, device="cuda") for d in X.dims]
     # 1024 FP64 rows of 32 columns: 272 KiB
     with pytest.raises(alto.AltoError):
         T.mttkrp(0, g32, plan=dict(conflict=alto.CR_TILE, table_slots=1024, block_threads=256))
-    # 1024 FP64 rows of 16 columns (144 KiB) + 512 threads x 16 B of staging
+    # 1024 FP64 rows of 16 columns (152 KiB with keys and counts) + 8 KiB of
+    # staging + 17 KiB of outboxes for 512 threads: too large
+    g16 = [torch.rand(d, 16, device="cuda") for d in X.dims]
+    with pytest.raises(alto.AltoError):
+        T.mttkrp(1, g16, plan=dict(conflict=alto.CR_TILE, table_slots=1024, block_threads=512))
+    # 512 such rows (76 KiB) fit
     facs = factors_for(X, 16, seed=17)
     gf = [torch.from_numpy(f).cuda() for f in facs]
-    got = T.mttkrp(1, gf, plan=dict(conflict=alto.CR_TILE, table_slots=1024, block_threads=512))
+    got = T.mttkrp(1, gf, plan=dict(conflict=alto.CR_TILE, table_slots=512, block_threads=512))
     say("[mttkrp] largest fitting table")
     check(got.cpu().numpy().astype(np.float64), oracle_modes(X, facs)[1], X, facs, 1, "largest table")
 
