@@ -269,6 +269,57 @@ def phi_leg(T, X, facs, rank, words, ev):
     return res
 
 
+def precision_report(T, X, coords, vals, facs0, rank, nsweeps, torch, alto, nrows=64, seed=40):
+    """The precision form over a whole run: ``nsweeps`` CP-ALS sweeps with
+    BF16 factor shadows.  Each MTTKRP of each sweep is redone from the inputs
+    the sweep gave it (modes before n updated, the others from the previous
+    sweep) and compared with (a) an FP64 reference on sampled rows, computed
+    here with float64 tensor ops over the nonzeros of those rows on the
+    BF16-rounded factors, and (b) the FP32-factor path on the FP32 factors
+    (whole matrix).  Relative Frobenius errors per sweep and mode, and for (a)
+    the worst entry's error over the sum of the absolute values of its terms
+    (rows with few terms of mixed sign have a large relative error at a tiny
+    absolute one)."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    v64 = vals.double()
+    subs = []
+    for n in range(X.nmodes):
+        rows = torch.unique(torch.randint(0, X.dims[n], (nrows,), generator=g)).cuda()
+        keep = torch.isin(coords[n], rows).nonzero().squeeze(1)
+        pos = torch.searchsorted(rows, coords[n][keep])
+        subs.append((rows, keep, pos))
+    work = [f.clone() for f in facs0]
+    lam = torch.empty(rank, dtype=torch.float64, device="cuda")
+    report = []
+    for k in range(nsweeps):
+        snap = [w.clone() for w in work]
+        T.sweep(work, lam=lam, fdt=alto.BF16)
+        e64, e32, w64 = [], [], []
+        for n in range(X.nmodes):
+            ins = [work[m] if m < n else snap[m] for m in range(X.nmodes)]
+            bf = [f.to(torch.bfloat16) for f in ins]
+            got = T.mttkrp(n, [b.view(torch.int16) for b in bf], out=torch.empty((X.dims[n], rank), device="cuda"),
+                           rank=rank, fdt=alto.BF16).double()
+            ref32 = T.mttkrp(n, ins, out=torch.empty((X.dims[n], rank), device="cuda")).double()
+            rows, keep, pos = subs[n]
+            term = v64[keep].unsqueeze(1).expand(-1, rank).clone()
+            for m in range(X.nmodes):
+                if m != n:
+                    term *= bf[m].double()[coords[m][keep]]
+            ref = torch.zeros((len(rows), rank), dtype=torch.float64, device="cuda").index_add_(0, pos, term)
+            scale = torch.zeros_like(ref).index_add_(0, pos, term.abs_())
+            e64.append(float((got[rows] - ref).norm() / ref.norm()))
+            w64.append(float(((got[rows] - ref).abs() / (scale + 1e-30)).max()))
+            e32.append(float((got - ref32).norm() / ref32.norm()))
+            del got, ref32, term, ref, scale
+        report.append({"sweep": k + 1, "vs_fp64_sampled_rows": [float(f"{e:.3e}") for e in e64],
+                       "worst_entry_err_over_abs_sum": [float(f"{e:.3e}") for e in w64],
+                       "vs_fp32_factor_path": [float(f"{e:.3e}") for e in e32]})
+        log(f"[bench] precision sweep {k + 1}: {report[-1]}")
+    return {"sweeps": report, "sampled_rows_per_mode": [len(s[0]) for s in subs],
+            "fp64_reference": "float64 tensor ops on the GPU over the nonzeros of the sampled rows, BF16-rounded factors"}
+
+
 def serving_run(njobs, nnz_hi, sweeps, load, budget_gb, max_active, seed=5):
     """The continuous-batching server on a Poisson stream of CP-ALS jobs.
     Returns a dict with sweep-latency percentiles and aggregate throughput."""
@@ -516,6 +567,7 @@ def main():
             bf16_err.append(float((ob - of).norm() / of.norm()))
             del ob, of
     phi = None if args.no_phi else phi_leg(T, X, facs0, rank, info_words, ev)
+    precision = precision_report(T, X, coords, vals, facs0, rank, nsweeps, torch, alto) if fdt == alto.BF16 else None
     T.free()
     torch.cuda.synchronize()
     tb = time.perf_counter()
@@ -588,6 +640,8 @@ def main():
         },
         "cpapr_phi": phi,
     }
+    if precision:
+        out["precision_form"] = precision
     if args.serve_jobs > 0:
         del coords, vals
         torch.cuda.empty_cache()
