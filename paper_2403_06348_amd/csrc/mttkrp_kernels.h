@@ -88,6 +88,50 @@ __device__ inline float4 bload4<uint16_t>(__amdgpu_buffer_rsrc_t r, uint32_t byt
     return bf16x4_to_float4(v[0], v[1]);
 }
 
+// Gathers kept in their stored form until used: the software-pipelined
+// loop issues a step's loads one step before its products, and widening
+// BF16 to FP32 right after the load would make the wave wait for it there.
+template <typename FT>
+struct Gathered;
+template <>
+struct Gathered<float> {
+    using T = float4;
+};
+template <>
+struct Gathered<uint16_t> {
+    using T = uint2;
+};
+
+template <typename FT>
+__device__ inline typename Gathered<FT>::T bload_raw(__amdgpu_buffer_rsrc_t r, uint32_t byte_off);
+
+template <>
+__device__ inline float4 bload_raw<float>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return bload4<float>(r, byte_off);
+}
+
+template <>
+__device__ inline uint2 bload_raw<uint16_t>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0);
+    return make_uint2(v[0], v[1]);
+}
+
+template <typename FT>
+__device__ inline typename Gathered<FT>::T load_raw(const void *base, uint64_t elem);
+
+template <>
+__device__ inline float4 load_raw<float>(const void *base, uint64_t elem) {
+    return load4<float>(base, elem);
+}
+
+template <>
+__device__ inline uint2 load_raw<uint16_t>(const void *base, uint64_t elem) {
+    return *(const uint2 *)((const uint16_t *)base + elem);
+}
+
+__device__ inline float4 widen(const float4 &v) { return v; }
+__device__ inline float4 widen(const uint2 &u) { return bf16x4_to_float4(u.x, u.y); }
+
 // Hardware id of the XCD (accelerator complex die) running this wave.
 __device__ inline uint32_t xcd_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 15u; }
 
@@ -261,11 +305,13 @@ __device__ inline Outbox outbox_of(uint32_t *obase, uint32_t *counts, int rank, 
 }
 
 // Add every row of the outbox to the output, the wave's active lanes taking
-// consecutive columns; empties the outbox.
+// consecutive columns; empties the outbox.  `n` is the entry count held in
+// a register (the same in every active lane); the LDS word mirrors it for
+// lanes that rejoin after leaving a loop early.
 template <bool FAST>
-__device__ inline void ob_drain(const Outbox &ob, const MttkrpArgs &a) {
+__device__ inline void ob_drain(const Outbox &ob, const MttkrpArgs &a, uint32_t &cnt) {
     __builtin_amdgcn_wave_barrier();
-    const uint32_t n = *ob.count;
+    const uint32_t n = cnt;
     if (n == 0) return;
     const uint64_t act = __activemask();
     const int me = __popcll(act & ((uint64_t(1) << (threadIdx.x & 63)) - 1));
@@ -278,6 +324,7 @@ __device__ inline void ob_drain(const Outbox &ob, const MttkrpArgs &a) {
         global_add1<FAST>(a, ob.rows[e], c, ob.vals[e * rk + c]);
     }
     __builtin_amdgcn_wave_barrier();
+    cnt = 0u;
     *ob.count = 0u;
     __builtin_amdgcn_wave_barrier();
 }
@@ -286,11 +333,11 @@ __device__ inline void ob_drain(const Outbox &ob, const MttkrpArgs &a) {
 // holds columns r0..r0+3 in acc) to the outbox.
 template <bool FAST>
 __device__ inline void ob_put(const Outbox &ob, const MttkrpArgs &a, bool want, uint32_t row, int q, int r0,
-                              const float *acc) {
+                              const float *acc, uint32_t &cnt) {
     const uint64_t bal = __ballot(want && q == 0);
     if (bal == 0) return;
     const int lane = threadIdx.x & 63;
-    const uint32_t n = *ob.count;
+    const uint32_t n = cnt;
     const int pos = (int)n + __popcll(bal & ((uint64_t(1) << (lane - q)) - 1));
     if (want) {
         if (pos < ob.cap) {
@@ -302,6 +349,7 @@ __device__ inline void ob_put(const Outbox &ob, const MttkrpArgs &a, bool want, 
     }
     __builtin_amdgcn_wave_barrier();
     const uint32_t nn = min((uint32_t)ob.cap, n + (uint32_t)__popcll(bal));
+    cnt = nn;
     *ob.count = nn;
     __builtin_amdgcn_wave_barrier();
 }
@@ -787,6 +835,7 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
     static_assert(MAXO == 2 || MAXO == 4, "pipelined stretch: up to 5 modes");
     static_assert(OP == kOpMttkrp || (MAXO == 4 && !FAST), "Phi forms use 8-word records");
     const int TM = TMC >= 0 ? TMC : a.tile_merge;
+    using GT = typename Gathered<FT>::T;
     constexpr int SB = MAXO == 2 ? (LPN < 4 ? LPN : 4) : (LPN < 2 ? LPN : 2);  // records per step
     constexpr int NS = LPN / SB;                                               // steps per batch
     constexpr int RW = MAXO == 2 ? 4 : 8;                                      // record words
@@ -814,6 +863,7 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
     __shared__ uint32_t ob_counts[16];
     if ((tid & 63) == 0) ob_counts[tid >> 6] = 0u;
     const Outbox ob = outbox_of(stage + (size_t)ngrp * LPN * RW, ob_counts, a.rank, LPN);
+    uint32_t obn = 0u;  // the wave's outbox entries (see ob_drain)
     constexpr int kGroupsPerWave = 64 / LPN;
     __amdgpu_buffer_rsrc_t rs[MAXO];
 #pragma unroll
@@ -905,7 +955,7 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
         };
         // step k: its records' heads, and the gathers of the other modes
         // (Phi forms: and of B's row of the output mode)
-        auto issue = [&](uint64_t k, float4 (&g)[MAXO][SB], uint32_t (&dv)[SB], float (&vv)[SB],
+        auto issue = [&](uint64_t k, GT (&g)[MAXO][SB], uint32_t (&dv)[SB], float (&vv)[SB],
                          float4 (&gB)[SB]) {
             if (k % NS == 0) {
                 decode(k / NS);
@@ -934,11 +984,11 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
                 for (int k2 = 0; k2 < MAXO; k2++) {
                     if (k2 < nother) {
                         if (buf32) {
-                            g[k2][s] = bload4<FT>(rs[k2], idx[k2] * ldb + colb);
+                            g[k2][s] = bload_raw<FT>(rs[k2], idx[k2] * ldb + colb);
                         } else {
                             const uint32_t ii = min(idx[k2], a.last_other[k2]);
-                            g[k2][s] = ract ? load4<FT>(a.fac_other[k2], (uint64_t)ii * a.ld + a.col0 + r0)
-                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+                            g[k2][s] = ract ? load_raw<FT>(a.fac_other[k2], (uint64_t)ii * a.ld + a.col0 + r0)
+                                            : GT{};
                         }
                     }
                 }
@@ -946,7 +996,7 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
         };
         // products of a step, merged into runs of equal destinations; a
         // finished run goes to its LDS slot, or to the wave's outbox
-        auto consume = [&](const float4 (&g)[MAXO][SB], const uint32_t (&dv)[SB], const float (&vv)[SB],
+        auto consume = [&](const GT (&g)[MAXO][SB], const uint32_t (&dv)[SB], const float (&vv)[SB],
                            const float4 (&gB)[SB]) {
 #pragma unroll
             for (int s = 0; s < SB; s++) {
@@ -956,10 +1006,11 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
 #pragma unroll
                 for (int k2 = 0; k2 < MAXO; k2++) {
                     if (k2 < nother) {
-                        p[0] *= g[k2][s].x;
-                        p[1] *= g[k2][s].y;
-                        p[2] *= g[k2][s].z;
-                        p[3] *= g[k2][s].w;
+                        const float4 gv = widen(g[k2][s]);
+                        p[0] *= gv.x;
+                        p[1] *= gv.y;
+                        p[2] *= gv.z;
+                        p[3] *= gv.w;
                     }
                 }
                 if constexpr (OP != kOpMttkrp) {
@@ -973,7 +1024,7 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
                 }
                 const bool same = live && dv[s] == cur;
                 const bool fl = live && !same && cur != kEmptyRow;
-                ob_put<FAST>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc);
+                ob_put<FAST>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc, obn);
                 if (fl && (cur & kSlotBit)) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
                 if (same) {
 #pragma unroll
@@ -983,11 +1034,11 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
 #pragma unroll
                     for (int j = 0; j < 4; j++) acc[j] = p[j];
                 }
-                if (*ob.count > (uint32_t)(ob.cap - kGroupsPerWave)) ob_drain<FAST>(ob, a);
+                if (obn > (uint32_t)(ob.cap - kGroupsPerWave)) ob_drain<FAST>(ob, a, obn);
             }
         };
 
-        float4 xg[MAXO][SB], yg[MAXO][SB];
+        GT xg[MAXO][SB], yg[MAXO][SB];
         float4 xb[SB], yb[SB];
         uint32_t xd[SB], yd[SB];
         float xv[SB], yv[SB];
@@ -1000,11 +1051,15 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
             consume(yg, yd, yv, yb);
         }
         {
+            // groups that left the step loop early rejoin here: the LDS word
+            // holds the count the last active lanes left
+            __builtin_amdgcn_wave_barrier();
+            obn = *(volatile uint32_t *)ob.count;
             const bool fl = cur != kEmptyRow;
-            ob_put<FAST>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc);
+            ob_put<FAST>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc, obn);
             if (fl && (cur & kSlotBit)) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
         }
-        ob_drain<FAST>(ob, a);
+        ob_drain<FAST>(ob, a, obn);
         __builtin_amdgcn_wave_barrier();
         tile_end<FAST>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
     }
