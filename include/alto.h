@@ -334,6 +334,35 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs /*host*/, con
                                   double *const *lambdas /*host[count] of device ptrs*/, void *stream);
 
 /*
+ * A batched sweep prepared once and run many times (Algorithm "alg:cp-als",
+ * the same sweep as cpd_als_sweep_batched; ranks multiples of 4, 4..64).
+ * alto_sweep_batch_create checks the items, allocates every workspace the
+ * sweep needs, resolves the MTTKRP plans (the first sight of a batch class
+ * times a few plans on `stream`, as cpd_als_sweep_batched does), uploads the
+ * per-job tables to device memory the batch owns, and synchronizes `stream`
+ * once.  alto_sweep_batch_run then enqueues one sweep of every item with
+ * kernel launches only -- no allocation, copy, memset or host
+ * synchronisation -- so it can be captured in a HIP graph and replayed; each
+ * run or replay updates the items' factors and lambdas in place, from
+ * whatever they hold when it starts.  The batch keeps the factor and lambda
+ * pointers, the handles and their workspaces: they must stay alive and in
+ * place while the batch (or a graph captured from it) is used.  A run
+ * returns ALTO_ERR_STATE, and a captured graph must not be replayed, once a
+ * handle's workspace was reallocated by a larger call on that handle.
+ * Items must be on the current device.  Runs on different streams must not
+ * overlap (they share the handles' workspaces).
+ * alto_sweep_batch_destroy releases the tables (after the last run's
+ * stream has passed them); NULL is accepted.
+ */
+typedef struct alto_sweep_batch *alto_sweep_batch_t;
+alto_status alto_sweep_batch_create(int count, const alto_handle *hs /*host*/, const int *ranks /*host*/,
+                                    const int *fdts /*host*/, float *const *const *factors /*host[count]*/,
+                                    double *const *lambdas /*host[count] of device ptrs*/, void *stream,
+                                    alto_sweep_batch_t *out /*host*/);
+alto_status alto_sweep_batch_run(alto_sweep_batch_t batch, void *stream);
+alto_status alto_sweep_batch_destroy(alto_sweep_batch_t batch);
+
+/*
  * ||X||_F^2 of the tensor (host double; synchronizes the stream).  Duplicate
  * coordinates count as one entry holding their sum: they are neighbours on
  * the ordered line, and the norm is the sum over runs of equal ALTO index of

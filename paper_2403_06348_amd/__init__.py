@@ -17,7 +17,8 @@ from ._capi import (  # noqa: F401
 )
 
 __all__ = [
-    "AltoError", "AltoTensor", "plan_dims", "plan_decode_host", "mttkrp_batched", "version", "F32", "BF16",
+    "AltoError", "AltoTensor", "plan_dims", "plan_decode_host", "mttkrp_batched", "sweep_batched", "SweepBatch",
+    "version", "F32", "BF16",
     "CR_AUTO", "CR_TILE", "CR_RUN", "CR_DIRECT", "CR_HOT", "ACC_DEFAULT", "ACC_F64", "ACC_F32", "ACC_XCD_F32", "ACC_XCD_F64",
 ]
 
@@ -347,3 +348,37 @@ def sweep_batched(items, stream=None):
     _check(_capi.lib().cpd_als_sweep_batched(count, hs, ranks, fdts, fptrs, lams, _stream(stream)),
            "cpd_als_sweep_batched")
     return [it[2] for it in items]
+
+
+class SweepBatch:
+    """A batched CP-ALS sweep prepared once (alto_sweep_batch_create) whose
+    run() enqueues kernels only, so it can be captured in a CUDA/HIP graph.
+    items as for sweep_batched; the tensors, factors and lambdas must stay
+    alive and in place while the batch is used."""
+
+    def __init__(self, items, stream=None):
+        count = len(items)
+        self._items = items  # keeps the tensors, factors and lambdas alive
+        hs = (ctypes.c_void_p * count)(*[it[0].handle.value for it in items])
+        ranks = (ctypes.c_int * count)(*[int(it[1][0].shape[1]) for it in items])
+        fdts = (ctypes.c_int * count)(*[int(it[3]) if len(it) > 3 else F32 for it in items])
+        farrs = [(ctypes.c_void_p * it[0].nmodes)(*[f.data_ptr() for f in it[1]]) for it in items]
+        fptrs = (ctypes.c_void_p * count)(*[ctypes.cast(a, ctypes.c_void_p).value for a in farrs])
+        lams = (ctypes.c_void_p * count)(*[it[2].data_ptr() for it in items])
+        self._b = ctypes.c_void_p()
+        _check(_capi.lib().alto_sweep_batch_create(count, hs, ranks, fdts, fptrs, lams, _stream(stream),
+                                                   ctypes.byref(self._b)), "alto_sweep_batch_create")
+
+    def run(self, stream=None):
+        _check(_capi.lib().alto_sweep_batch_run(self._b, _stream(stream)), "alto_sweep_batch_run")
+
+    def close(self):
+        if self._b:
+            _check(_capi.lib().alto_sweep_batch_destroy(self._b), "alto_sweep_batch_destroy")
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

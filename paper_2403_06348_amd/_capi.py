@@ -155,6 +155,9 @@ SIGNATURES = {
     "alto_cp_fit": (I32, [P, I32, I32, P, P, ctypes.POINTER(ctypes.c_double), P]),
     "cpd_als": (I32, [P, I32, I32, P, P, I32, ctypes.c_double, P, ctypes.POINTER(I32), P]),
     "cpd_als_sweep_batched": (I32, [I32, P, P, P, P, P, P]),
+    "alto_sweep_batch_create": (I32, [I32, P, P, P, P, P, P, ctypes.POINTER(P)]),
+    "alto_sweep_batch_run": (I32, [P, P]),
+    "alto_sweep_batch_destroy": (I32, [P]),
     "alto_server_create": (I32, [U64, I32, ctypes.POINTER(P)]),
     "alto_server_submit": (I32, [P, ctypes.POINTER(ServeJob)]),
     "alto_server_poll": (I32, [P, P, I32, ctypes.POINTER(I32)]),

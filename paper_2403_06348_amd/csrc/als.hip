@@ -18,7 +18,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -36,12 +38,6 @@ constexpr int kPartials = kSweepPartials;  // partial Gram blocks
 constexpr int kMaxSweepRank = 64;
 constexpr int kMaxPairs = kMaxSweepRank / 2;  // Jacobi rotations per step
 static_assert(kThreads == 8 * kMaxPairs && kMaxSweepRank <= 64, "Jacobi step thread layout: 32 x 8 blocks, 4 x 64 Q rows");
-// A job this large runs its MTTKRPs in launches of its own (its mode's plan:
-// whole-mode LDS, rank tiles); smaller ones share the batched launches.
-// Measured on a 256-job serving stream: 2^21 -> 2^23 cut the sweep latency
-// p50/p99 from 27/58 to 17/54 ms.
-constexpr uint64_t kBatchAloneNnz = uint64_t(1) << 23;
-
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
     const uint32_t u = __float_as_uint(f);
     if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));  // inf / nan
@@ -769,9 +765,294 @@ alto_status sweep_run(alto_tensor *h, int rank, int rank_true, int fdt, float *c
     return ALTO_OK;
 }
 
+// ---- batched sweeps (many tensors, interleaved mode by mode)
+
+namespace {
+
+// The host description of one batched sweep: the jobs, and the table of
+// their per-mode R x R steps (section m: the jobs that have a mode m).
+struct BatchedSweep {
+    int count = 0, maxN = 0, maxR = 0;
+    std::vector<alto_tensor *> hs;
+    std::vector<int> ranks, fdts;
+    std::vector<float *> facs;         // count x ALTO_MAX_MODES factor pointers
+    std::vector<double *> lambdas;
+    std::vector<const void *> fptr;    // count x ALTO_MAX_MODES gathered factors (BF16 shadows)
+    std::vector<SweepJob> table;
+    std::vector<size_t> sec;
+    unsigned nblk = 1, rblocks = 1;
+};
+
+// A job that fills the GPU by itself runs its own MTTKRP launch with its
+// mode's plan (whole-mode LDS, rank tiles); the small ones share persistent
+// launches.
+bool runs_alone(const alto_tensor *h) { return h->info.nnz >= kBatchAloneNnz; }
+
+// Such a job accumulates in FP32 or in one FP64 buffer (dims x rank doubles,
+// which the serving footprint counts), never in per-XCD copies.
+void batched_alone_accumulation(alto_mttkrp_plan *p) {
+    if (p->accumulate == ALTO_ACC_XCD_F64 || p->accumulate == ALTO_ACC_XCD_F32) p->accumulate = ALTO_ACC_F64;
+}
+
+}  // namespace
+
 }  // namespace alto
 
 using namespace alto;
+
+// A batched sweep prepared once: its device tables (the R x R step table and
+// the planned MTTKRP groups of every mode) and the alone jobs' plans, so that
+// a run only launches kernels.
+struct alto_sweep_batch {
+    static constexpr uint32_t kMagic = 0x53574250u;
+    uint32_t magic = kMagic;
+    int device = 0;
+    BatchedSweep bs;
+    std::vector<std::vector<std::pair<int, alto_mttkrp_plan>>> alone;  // per mode: (job, plan)
+    std::vector<std::vector<GroupLaunch>> groups;                      // per mode
+    std::vector<std::vector<size_t>> offs;                             // their blob offsets
+    std::vector<char> host;                                            // the device tables' image
+    void *dev = nullptr;
+    hipStream_t last = nullptr;
+    // each handle's workspaces when the tables were built (they point there)
+    std::vector<std::array<const void *, 4 + ALTO_MAX_MODES>> ws;
+};
+
+namespace {
+
+std::array<const void *, 4 + ALTO_MAX_MODES> ws_of(const alto_tensor *h) {
+    std::array<const void *, 4 + ALTO_MAX_MODES> w{};
+    w[0] = h->ws_sweep;
+    w[1] = h->ws_m;
+    w[2] = h->ws_flags;
+    w[3] = h->ws_acc;
+    for (int m = 0; m < h->info.nmodes; m++) w[4 + m] = h->ws_bf16[m];
+    return w;
+}
+
+// Validation, workspaces and the step table of a batched sweep.
+alto_status batched_sweep_setup(int count, const alto_handle *hs, const int *ranks, const int *fdts,
+                                float *const *const *factors, double *const *lambdas, hipStream_t s,
+                                BatchedSweep *bs) {
+    if (!hs || !ranks || !fdts || !factors || !lambdas) return fail(ALTO_ERR_ARG, "NULL argument");
+    bs->count = count;
+    bs->hs.assign(hs, hs + count);
+    bs->ranks.assign(ranks, ranks + count);
+    bs->fdts.assign(fdts, fdts + count);
+    bs->lambdas.assign(lambdas, lambdas + count);
+    bs->facs.assign((size_t)count * ALTO_MAX_MODES, nullptr);
+    for (int j = 0; j < count; j++) {
+        if (!factors[j]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(j) + "] is NULL");
+        alto_status st = sweep_setup(hs[j], ranks[j], fdts[j], factors[j], lambdas[j], s);
+        if (st != ALTO_OK) return fail(st, "item " + std::to_string(j) + ": " + alto_last_error());
+        bs->maxN = std::max(bs->maxN, hs[j]->info.nmodes);
+        bs->maxR = std::max(bs->maxR, ranks[j]);
+        for (int m = 0; m < hs[j]->info.nmodes; m++) bs->facs[(size_t)j * ALTO_MAX_MODES + m] = factors[j][m];
+    }
+    const int maxN = bs->maxN;
+    bs->sec.assign(maxN + 1, 0);
+    for (int m = 0; m < maxN; m++) {
+        bs->sec[m] = bs->table.size();
+        for (int j = 0; j < count; j++) {
+            alto_tensor *h = hs[j];
+            if (m >= h->info.nmodes) continue;
+            const int R = ranks[j];
+            const size_t rr = (size_t)R * R;
+            double *grams = (double *)h->ws_sweep;
+            double *W = grams + h->info.nmodes * rr;
+            double *partials = W + rr;
+            SweepJob jb;
+            jb.grams = grams;
+            jb.W = W;
+            jb.flags = h->ws_flags;
+            jb.partials = partials;
+            jb.G = grams + m * rr;
+            jb.lam_ws = partials + (size_t)kPartials * rr;
+            jb.lam_out = m == h->info.nmodes - 1 ? lambdas[j] : nullptr;
+            jb.A = factors[j][m];
+            jb.shadow = fdts[j] == ALTO_BF16 ? h->ws_bf16[m] : nullptr;
+            jb.I = h->info.dims[m];
+            jb.N = h->info.nmodes;
+            jb.n = m;
+            jb.R = R;
+            jb.P = (int)partial_blocks(jb.I);
+            bs->table.push_back(jb);
+        }
+    }
+    bs->sec[maxN] = bs->table.size();
+    // normalization workgroups per job: enough for the largest factor
+    uint64_t maxIR = 1;
+    for (const SweepJob &jb : bs->table) maxIR = std::max<uint64_t>(maxIR, jb.I * (uint64_t)jb.R);
+    bs->nblk = (unsigned)std::min<uint64_t>(512, (maxIR + 2047) / 2048);
+    bs->rblocks = gram_reduce_blocks(bs->maxR);
+    bs->fptr.assign((size_t)count * ALTO_MAX_MODES, nullptr);
+    for (int j = 0; j < count; j++)
+        sweep_factor_ptrs(hs[j], fdts[j], &bs->facs[(size_t)j * ALTO_MAX_MODES], &bs->fptr[(size_t)j * ALTO_MAX_MODES]);
+    return ALTO_OK;
+}
+
+// The launch sequence of a batched sweep.  With a prepared batch `pb`, the
+// MTTKRPs use its plans and device tables (kernel launches only); without,
+// plans are resolved and the group tables uploaded now.
+alto_status batched_sweep_launch(const BatchedSweep &bs, const SweepJob *dtab, const alto_sweep_batch *pb,
+                                 const char *dbase, hipStream_t s) {
+    const int count = bs.count;
+    // Grams of every factor: the partials of mode m for every job, then one
+    // reduction launch (each job's partial buffer is reused mode by mode)
+    for (int m = 0; m < bs.maxN; m++) {
+        for (int j = 0; j < count; j++)
+            if (m < bs.hs[j]->info.nmodes)
+                gram_partials(bs.hs[j], m, bs.ranks[j], bs.fdts[j], &bs.facs[(size_t)j * ALTO_MAX_MODES], s);
+        const unsigned nj = (unsigned)(bs.sec[m + 1] - bs.sec[m]);
+        hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, bs.rblocks), dim3(kThreads), 0, s, dtab + bs.sec[m]);
+    }
+    ALTO_HIP(hipGetLastError());
+    std::vector<alto_handle> bh;
+    std::vector<int> bm, br, bf;
+    std::vector<const void *const *> bfac;
+    std::vector<float *> bout;
+    for (int n = 0; n < bs.maxN; n++) {
+        const unsigned nj = (unsigned)(bs.sec[n + 1] - bs.sec[n]);
+        // V, Cholesky and solve operator of mode n for every job
+        hipLaunchKernelGGL(k_als_prepare_b, dim3(nj), dim3(kThreads), prepare_lds_bytes(bs.maxR), s,
+                           dtab + bs.sec[n]);
+        ALTO_HIP(hipGetLastError());
+        alto_status st = ALTO_OK;
+        if (pb) {
+            for (const auto &jp : pb->alone[n]) {
+                const int j = jp.first;
+                st = run_mttkrp(bs.hs[j], n, bs.ranks[j], bs.fdts[j], &bs.fptr[(size_t)j * ALTO_MAX_MODES],
+                                bs.hs[j]->ws_m, jp.second, s);
+                if (st != ALTO_OK) return st;
+            }
+            for (size_t k = 0; k < pb->groups[n].size(); k++) {
+                st = launch_planned_group(pb->groups[n][k], dbase + pb->offs[n][k], s);
+                if (st != ALTO_OK) return st;
+            }
+        } else {
+            bh.clear(); bm.clear(); br.clear(); bf.clear(); bfac.clear(); bout.clear();
+            for (int j = 0; j < count; j++) {
+                if (n >= bs.hs[j]->info.nmodes) continue;
+                if (runs_alone(bs.hs[j])) {
+                    alto_mttkrp_plan p;
+                    st = resolve_plan(bs.hs[j], n, bs.ranks[j], bs.fdts[j], nullptr, &p);
+                    if (st != ALTO_OK) return st;
+                    batched_alone_accumulation(&p);
+                    st = run_mttkrp(bs.hs[j], n, bs.ranks[j], bs.fdts[j], &bs.fptr[(size_t)j * ALTO_MAX_MODES],
+                                    bs.hs[j]->ws_m, p, s);
+                    if (st != ALTO_OK) return st;
+                    continue;
+                }
+                bh.push_back(bs.hs[j]);
+                bm.push_back(n);
+                br.push_back(bs.ranks[j]);
+                bf.push_back(bs.fdts[j]);
+                bfac.push_back(&bs.fptr[(size_t)j * ALTO_MAX_MODES]);
+                bout.push_back(bs.hs[j]->ws_m);
+            }
+            // the MTTKRPs of mode n of every job in one persistent launch per
+            // kernel variant
+            st = bh.empty() ? ALTO_OK
+                            : batched_run((int)bh.size(), bh.data(), bm.data(), br.data(), bf.data(), bfac.data(),
+                                          bout.data(), s);
+            if (st != ALTO_OK) return st;
+        }
+        // A = M W with the partial Grams of A, per job (the real work), then
+        // the Gram sums, lambda and normalization in one launch each
+        for (int j = 0; j < count; j++) {
+            if (n >= bs.hs[j]->info.nmodes) continue;
+            alto_tensor *h = bs.hs[j];
+            const int R = bs.ranks[j];
+            const size_t rr = (size_t)R * R;
+            double *W = (double *)h->ws_sweep + h->info.nmodes * rr;
+            const uint64_t I = h->info.dims[n];
+            launch_gram_rows<true>(R, partial_blocks(I), s, h->ws_m, W, bs.facs[(size_t)j * ALTO_MAX_MODES + n], I,
+                                   W + rr);
+        }
+        hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, bs.rblocks), dim3(kThreads), 0, s, dtab + bs.sec[n]);
+        hipLaunchKernelGGL(k_als_finalize_b, dim3(nj), dim3(kThreads), 0, s, dtab + bs.sec[n]);
+        hipLaunchKernelGGL(k_als_normalize_b, dim3(nj, bs.nblk), dim3(256), 0, s, dtab + bs.sec[n]);
+        ALTO_HIP(hipGetLastError());
+    }
+    return ALTO_OK;
+}
+
+// Plans, reserved workspaces and device tables of a prepared batch.
+alto_status batched_sweep_prepare(alto_sweep_batch *b, hipStream_t s) {
+    BatchedSweep &bs = b->bs;
+    const int maxN = bs.maxN;
+    b->alone.assign(maxN, {});
+    b->groups.assign(maxN, {});
+    b->offs.assign(maxN, {});
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = align(bs.table.size() * sizeof(SweepJob));
+    std::vector<alto_handle> bh;
+    std::vector<int> bm, br, bf;
+    std::vector<const void *const *> bfac;
+    std::vector<float *> bout;
+    for (int n = 0; n < maxN; n++) {
+        bh.clear(); bm.clear(); br.clear(); bf.clear(); bfac.clear(); bout.clear();
+        for (int j = 0; j < bs.count; j++) {
+            alto_tensor *h = bs.hs[j];
+            if (n >= h->info.nmodes) continue;
+            if (runs_alone(h)) {
+                alto_mttkrp_plan p;
+                alto_status st = resolve_plan(h, n, bs.ranks[j], bs.fdts[j], nullptr, &p);
+                if (st != ALTO_OK) return st;
+                batched_alone_accumulation(&p);
+                if (p.accumulate != ALTO_ACC_F32) {
+                    // the accumulation buffer the run will use, allocated now
+                    const bool f64 = p.accumulate == ALTO_ACC_F64 || p.accumulate == ALTO_ACC_XCD_F64;
+                    const int copies = (p.accumulate == ALTO_ACC_XCD_F32 || p.accumulate == ALTO_ACC_XCD_F64) ? kXcdCopies : 1;
+                    st = ensure_ws(&h->ws_acc, &h->ws_acc_bytes,
+                                   h->info.dims[n] * (size_t)bs.ranks[j] * copies * (f64 ? 8 : 4), s);
+                    if (st != ALTO_OK) return st;
+                }
+                b->alone[n].push_back({j, p});
+                continue;
+            }
+            bh.push_back(h);
+            bm.push_back(n);
+            br.push_back(bs.ranks[j]);
+            bf.push_back(bs.fdts[j]);
+            bfac.push_back(&bs.fptr[(size_t)j * ALTO_MAX_MODES]);
+            bout.push_back(h->ws_m);
+        }
+        if (bh.empty()) continue;
+        alto_status st = batched_plan((int)bh.size(), bh.data(), bm.data(), br.data(), bf.data(), bfac.data(),
+                                      bout.data(), s, &b->groups[n]);
+        if (st != ALTO_OK) return st;
+        for (const GroupLaunch &gl : b->groups[n]) {
+            b->offs[n].push_back(off);
+            off += align(gl.blob_bytes());
+        }
+    }
+    b->host.assign(off, 0);
+    memcpy(b->host.data(), bs.table.data(), bs.table.size() * sizeof(SweepJob));
+    for (int n = 0; n < maxN; n++)
+        for (size_t k = 0; k < b->groups[n].size(); k++) b->groups[n][k].write_blob(b->host.data() + b->offs[n][k]);
+    if (dev_alloc(&b->dev, off) != hipSuccess) return fail(ALTO_ERR_OOM, "sweep batch table allocation failed");
+    b->last = s;
+    ALTO_HIP(hipMemcpyAsync(b->dev, b->host.data(), off, hipMemcpyHostToDevice, s));
+    ALTO_HIP(hipStreamSynchronize(s));
+    b->ws.clear();
+    for (int j = 0; j < bs.count; j++) b->ws.push_back(ws_of(bs.hs[j]));
+    return ALTO_OK;
+}
+
+// The tables point into the handles' workspaces: a run is refused once any
+// of them was reallocated (by a larger call on the same handle).
+alto_status batched_sweep_check(const alto_sweep_batch *b) {
+    for (int j = 0; j < b->bs.count; j++) {
+        ALTO_CHECK_HANDLE(b->bs.hs[j]);
+        if (ws_of(b->bs.hs[j]) != b->ws[j])
+            return fail(ALTO_ERR_STATE, "sweep batch item " + std::to_string(j) +
+                                            ": the handle's workspace changed since the batch was created");
+    }
+    return ALTO_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -801,121 +1082,58 @@ alto_status cpd_als_sweep_batched(int count, const alto_handle *hs, const int *r
                                   float *const *const *factors, double *const *lambdas, void *stream) {
     if (count < 0) return fail(ALTO_ERR_ARG, "count < 0");
     if (count == 0) return ALTO_OK;
-    if (!hs || !ranks || !fdts || !factors || !lambdas) return fail(ALTO_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    int maxN = 0, maxR = 0;
-    for (int j = 0; j < count; j++) {
-        if (!factors[j]) return fail(ALTO_ERR_ARG, "factors[" + std::to_string(j) + "] is NULL");
-        alto_status st = sweep_setup(hs[j], ranks[j], fdts[j], factors[j], lambdas[j], s);
-        if (st != ALTO_OK) return fail(st, "item " + std::to_string(j) + ": " + alto_last_error());
-        maxN = std::max(maxN, hs[j]->info.nmodes);
-        maxR = std::max(maxR, ranks[j]);
-    }
-    // The per-job R x R steps of every mode, in one table uploaded once:
-    // section m holds the jobs that have a mode m, in job order.
-    std::vector<SweepJob> table;
-    std::vector<size_t> sec(maxN + 1, 0);
-    for (int m = 0; m < maxN; m++) {
-        sec[m] = table.size();
-        for (int j = 0; j < count; j++) {
-            alto_tensor *h = hs[j];
-            if (m >= h->info.nmodes) continue;
-            const int R = ranks[j];
-            const size_t rr = (size_t)R * R;
-            double *grams = (double *)h->ws_sweep;
-            double *W = grams + h->info.nmodes * rr;
-            double *partials = W + rr;
-            SweepJob jb;
-            jb.grams = grams;
-            jb.W = W;
-            jb.flags = h->ws_flags;
-            jb.partials = partials;
-            jb.G = grams + m * rr;
-            jb.lam_ws = partials + (size_t)kPartials * rr;
-            jb.lam_out = m == h->info.nmodes - 1 ? lambdas[j] : nullptr;
-            jb.A = factors[j][m];
-            jb.shadow = fdts[j] == ALTO_BF16 ? h->ws_bf16[m] : nullptr;
-            jb.I = h->info.dims[m];
-            jb.N = h->info.nmodes;
-            jb.n = m;
-            jb.R = R;
-            jb.P = (int)partial_blocks(jb.I);
-            table.push_back(jb);
-        }
-    }
-    sec[maxN] = table.size();
-    // normalization workgroups per job: enough for the largest factor
-    uint64_t maxIR = 1;
-    for (const SweepJob &jb : table) maxIR = std::max<uint64_t>(maxIR, jb.I * (uint64_t)jb.R);
-    const unsigned nblk = (unsigned)std::min<uint64_t>(512, (maxIR + 2047) / 2048);
-    SweepJob *dtab = nullptr;
-    alto_status st = upload_sweep_jobs(table, s, &dtab);
+    BatchedSweep bs;
+    alto_status st = batched_sweep_setup(count, hs, ranks, fdts, factors, lambdas, s, &bs);
     if (st != ALTO_OK) return st;
-    const unsigned rblocks = gram_reduce_blocks(maxR);
-    // Grams of every factor: the partials of mode m for every job, then one
-    // reduction launch (each job's partial buffer is reused mode by mode)
-    for (int m = 0; m < maxN; m++) {
-        for (int j = 0; j < count; j++)
-            if (m < hs[j]->info.nmodes) gram_partials(hs[j], m, ranks[j], fdts[j], factors[j], s);
-        const unsigned nj = (unsigned)(sec[m + 1] - sec[m]);
-        hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, rblocks), dim3(kThreads), 0, s, dtab + sec[m]);
+    SweepJob *dtab = nullptr;
+    st = upload_sweep_jobs(bs.table, s, &dtab);
+    if (st != ALTO_OK) return st;
+    return batched_sweep_launch(bs, dtab, nullptr, nullptr, s);
+}
+
+alto_status alto_sweep_batch_create(int count, const alto_handle *hs, const int *ranks, const int *fdts,
+                                    float *const *const *factors, double *const *lambdas, void *stream,
+                                    alto_sweep_batch_t *out) {
+    if (!out) return fail(ALTO_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1) return fail(ALTO_ERR_ARG, "count must be at least 1");
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<alto_sweep_batch> b(new alto_sweep_batch());
+    alto_status st = batched_sweep_setup(count, hs, ranks, fdts, factors, lambdas, s, &b->bs);
+    if (st != ALTO_OK) return st;
+    ALTO_HIP(hipGetDevice(&b->device));
+    for (int j = 0; j < count; j++)
+        if (hs[j]->device != b->device) return fail(ALTO_ERR_ARG, "every handle must be on the current device");
+    st = batched_sweep_prepare(b.get(), s);
+    if (st != ALTO_OK) return st;
+    *out = b.release();
+    return ALTO_OK;
+}
+
+alto_status alto_sweep_batch_run(alto_sweep_batch_t b, void *stream) {
+    if (!b || b->magic != alto_sweep_batch::kMagic) return fail(ALTO_ERR_STATE, "not a sweep batch");
+    hipStream_t s = (hipStream_t)stream;
+    int dev = -1;
+    ALTO_HIP(hipGetDevice(&dev));
+    if (dev != b->device) return fail(ALTO_ERR_ARG, "the batch's device is not the current device");
+    alto_status st = batched_sweep_check(b);
+    if (st != ALTO_OK) return st;
+    for (int j = 0; j < b->bs.count; j++) {
+        b->bs.hs[j]->stream = s;
+        hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, b->bs.hs[j]->ws_flags, (uint64_t)1, 0u);
     }
     ALTO_HIP(hipGetLastError());
-    std::vector<const void *> fptr((size_t)count * ALTO_MAX_MODES);
-    for (int j = 0; j < count; j++) sweep_factor_ptrs(hs[j], fdts[j], factors[j], &fptr[(size_t)j * ALTO_MAX_MODES]);
-    // a job that fills the GPU by itself runs its own launch with its mode's
-    // plan (whole-mode LDS, rank tiles); the small ones share persistent
-    // launches
-    auto alone = [&](int j) { return hs[j]->info.nnz >= kBatchAloneNnz; };
-    std::vector<alto_handle> bh;
-    std::vector<int> bm, br, bf;
-    std::vector<const void *const *> bfac;
-    std::vector<float *> bout;
-    for (int n = 0; n < maxN; n++) {
-        const unsigned nj = (unsigned)(sec[n + 1] - sec[n]);
-        // V, Cholesky and solve operator of mode n for every job
-        hipLaunchKernelGGL(k_als_prepare_b, dim3(nj), dim3(kThreads), prepare_lds_bytes(maxR), s, dtab + sec[n]);
-        ALTO_HIP(hipGetLastError());
-        bh.clear(); bm.clear(); br.clear(); bf.clear(); bfac.clear(); bout.clear();
-        for (int j = 0; j < count; j++) {
-            if (n >= hs[j]->info.nmodes) continue;
-            if (alone(j)) {
-                alto_mttkrp_plan p;
-                st = resolve_plan(hs[j], n, ranks[j], fdts[j], nullptr, &p);
-                if (st != ALTO_OK) return st;
-                st = run_mttkrp(hs[j], n, ranks[j], fdts[j], &fptr[(size_t)j * ALTO_MAX_MODES], hs[j]->ws_m, p, s);
-                if (st != ALTO_OK) return st;
-                continue;
-            }
-            bh.push_back(hs[j]);
-            bm.push_back(n);
-            br.push_back(ranks[j]);
-            bf.push_back(fdts[j]);
-            bfac.push_back(&fptr[(size_t)j * ALTO_MAX_MODES]);
-            bout.push_back(hs[j]->ws_m);
-        }
-        // the MTTKRPs of mode n of every job in one persistent launch per
-        // kernel variant
-        st = bh.empty() ? ALTO_OK
-                        : batched_run((int)bh.size(), bh.data(), bm.data(), br.data(), bf.data(), bfac.data(),
-                                      bout.data(), s);
-        if (st != ALTO_OK) return st;
-        // A = M W with the partial Grams of A, per job (the real work), then
-        // the Gram sums, lambda and normalization in one launch each
-        for (int j = 0; j < count; j++) {
-            if (n >= hs[j]->info.nmodes) continue;
-            alto_tensor *h = hs[j];
-            const int R = ranks[j];
-            const size_t rr = (size_t)R * R;
-            double *W = (double *)h->ws_sweep + h->info.nmodes * rr;
-            const uint64_t I = h->info.dims[n];
-            launch_gram_rows<true>(R, partial_blocks(I), s, h->ws_m, W, factors[j][n], I, W + rr);
-        }
-        hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, rblocks), dim3(kThreads), 0, s, dtab + sec[n]);
-        hipLaunchKernelGGL(k_als_finalize_b, dim3(nj), dim3(kThreads), 0, s, dtab + sec[n]);
-        hipLaunchKernelGGL(k_als_normalize_b, dim3(nj, nblk), dim3(256), 0, s, dtab + sec[n]);
-        ALTO_HIP(hipGetLastError());
-    }
+    b->last = s;
+    return batched_sweep_launch(b->bs, (const SweepJob *)b->dev, b, (const char *)b->dev, s);
+}
+
+alto_status alto_sweep_batch_destroy(alto_sweep_batch_t b) {
+    if (!b) return ALTO_OK;
+    if (b->magic != alto_sweep_batch::kMagic) return fail(ALTO_ERR_STATE, "not a sweep batch");
+    b->magic = 0;
+    if (b->dev) dev_free_after(b->dev, b->last);
+    delete b;
     return ALTO_OK;
 }
 

@@ -16,19 +16,6 @@
 namespace alto {
 namespace {
 
-// Per-stream device staging of job descriptors: calls on one stream reuse
-// its buffer in stream order; calls on different streams never share one.
-struct Staging {
-    void *dev = nullptr;
-    size_t bytes = 0;
-};
-std::mutex g_stage_mu;
-std::map<std::pair<int, hipStream_t>, Staging> g_stage;
-
-// Tuned (tile, table rows) per kernel-variant group and total-size class.
-std::mutex g_btune_mu;
-std::map<std::array<int, 6>, std::pair<int, int>> g_btune;
-
 struct Group {
     int lpn, fdt, words, maxo;
     std::vector<int> items;
@@ -36,12 +23,16 @@ struct Group {
 
 int maxo_of(int nmodes) { return nmodes <= 3 ? 2 : (nmodes <= 5 ? 4 : 7); }
 
-alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes, const int *ranks,
-                         const void *const *const *factors, float *const *outs, int tile, int slots_factor,
-                         hipStream_t s, int dev) {
+// Host side of one group's persistent launch: the per-job kernel arguments,
+// tile and output prefixes, LDS size and kernel.
+alto_status plan_group(const Group &g, const alto_handle *hs, const int *modes, const int *ranks,
+                       const void *const *const *factors, float *const *outs, int tile, int slots_factor,
+                       hipStream_t s, int dev, GroupLaunch *gl) {
     const int nj = (int)g.items.size();
-    std::vector<MttkrpArgs> jobs(nj);
-    std::vector<uint64_t> prefix(nj + 1, 0), oprefix(nj + 1, 0);
+    gl->nj = nj;
+    gl->jobs.assign(nj, MttkrpArgs{});
+    gl->prefix.assign(nj + 1, 0);
+    gl->oprefix.assign(nj + 1, 0);
     size_t lds = 0;
     for (int k = 0; k < nj; k++) {
         const int j = g.items[k];
@@ -59,15 +50,51 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
         // 96 KiB of FP64 rows, keys and hit counts
         while (p.table_slots > 16 && (size_t)p.table_slots * (2 * (ranks[j] + 1) + 2) * 4 > 96 * 1024)
             p.table_slots /= 2;
-        fill_args(h, modes[j], ranks[j], g.fdt, factors[j], p, outs[j], nullptr, &jobs[k]);
-        jobs[k].xcd_map = 0;
-        const uint64_t tiles = h->info.nnz == 0 ? 0 : jobs[k].ntiles;
-        prefix[k + 1] = prefix[k] + tiles;
-        oprefix[k + 1] = oprefix[k] + h->info.dims[modes[j]] * (uint64_t)ranks[j];
-        lds = std::max(lds, lds_bytes(jobs[k], 256));
+        fill_args(h, modes[j], ranks[j], g.fdt, factors[j], p, outs[j], nullptr, &gl->jobs[k]);
+        gl->jobs[k].xcd_map = 0;
+        const uint64_t tiles = h->info.nnz == 0 ? 0 : gl->jobs[k].ntiles;
+        gl->prefix[k + 1] = gl->prefix[k] + tiles;
+        gl->oprefix[k + 1] = gl->oprefix[k] + h->info.dims[modes[j]] * (uint64_t)ranks[j];
+        lds = std::max(lds, lds_bytes(gl->jobs[k], 256));
     }
-    const size_t jb = sizeof(MttkrpArgs) * nj, pb = 8 * (nj + 1);
-    const size_t need = jb + 2 * pb;
+    gl->lds = lds;
+    gl->kern = pick_kernel(g.lpn, g.fdt, g.words, gl->jobs[0].nmodes, true);
+    if (gl->prefix[nj] == 0) return ALTO_OK;
+    alto_status lst = check_launch_lds(gl->kern, lds, dev);
+    if (lst != ALTO_OK) return lst;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gl->kern, 256, lds) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        occ = 1;
+    }
+    uint64_t grid = (uint64_t)device_cus(dev) * occ;
+    gl->xcd_map = 1;
+    if (grid >= gl->prefix[nj]) {
+        grid = gl->prefix[nj];
+        gl->xcd_map = 0;
+    } else {
+        grid = grid / 8 * 8;
+    }
+    gl->grid = (unsigned)grid;
+    return ALTO_OK;
+}
+
+// Per-stream device staging of job descriptors: calls on one stream reuse
+// its buffer in stream order; calls on different streams never share one.
+struct Staging {
+    void *dev = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_stage_mu;
+std::map<std::pair<int, hipStream_t>, Staging> g_stage;
+
+alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes, const int *ranks,
+                         const void *const *const *factors, float *const *outs, int tile, int slots_factor,
+                         hipStream_t s, int dev) {
+    GroupLaunch gl;
+    alto_status st0 = plan_group(g, hs, modes, ranks, factors, outs, tile, slots_factor, s, dev, &gl);
+    if (st0 != ALTO_OK) return st0;
+    const size_t need = gl.blob_bytes();
     Staging *st;
     {
         std::lock_guard<std::mutex> lk(g_stage_mu);
@@ -83,49 +110,21 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
         st->bytes = need;
     }
     std::vector<char> host(need);
-    memcpy(host.data(), jobs.data(), jb);
-    memcpy(host.data() + jb, prefix.data(), pb);
-    memcpy(host.data() + jb + pb, oprefix.data(), pb);
+    gl.write_blob(host.data());
     ALTO_HIP(hipMemcpyAsync(st->dev, host.data(), need, hipMemcpyHostToDevice, s));
-    const MttkrpArgs *djobs = (const MttkrpArgs *)st->dev;
-    const uint64_t *dprefix = (const uint64_t *)((char *)st->dev + jb);
-    const uint64_t *doprefix = (const uint64_t *)((char *)st->dev + jb + pb);
-    {
-        void *args[] = {(void *)&djobs, (void *)&doprefix, (void *)&nj};
-        const unsigned g0 = grid_for(oprefix[nj], 256, 8192);
-        ALTO_HIP(hipLaunchKernel(zero_outputs_kernel(), dim3(g0), dim3(256), args, 0, s));
-    }
-    if (prefix[nj] == 0) return ALTO_OK;
-    const void *kern = pick_kernel(g.lpn, g.fdt, g.words, jobs[0].nmodes, true);
-    alto_status lst = check_launch_lds(kern, lds, dev);
-    if (lst != ALTO_OK) return lst;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1) {
-        (void)hipGetLastError();
-        occ = 1;
-    }
-    uint64_t grid = (uint64_t)device_cus(dev) * occ;
-    int xcd_map = 1;
-    if (grid >= prefix[nj]) {
-        grid = prefix[nj];
-        xcd_map = 0;
-    } else {
-        grid = grid / 8 * 8;
-    }
-    void *args[] = {(void *)&djobs, (void *)&dprefix, (void *)&nj, (void *)&xcd_map};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timed = timing_begin(s, &e0, &e1);
-    ALTO_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(256), args, lds, s));
-    if (timed) timing_end(s, e0, e1);
-    return ALTO_OK;
+    return launch_planned_group(gl, st->dev, s);
 }
 
-}  // namespace
+// Tuned (tile, table rows) per kernel-variant group and total-size class.
+std::mutex g_btune_mu;
+std::map<std::array<int, 6>, std::pair<int, int>> g_btune;
 
-alto_status batched_run(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
-                        const void *const *const *factors, float *const *outs, hipStream_t s) {
-    int dev = 0;
-    ALTO_HIP(hipGetDevice(&dev));
+// Groups of the items by kernel variant, each with its tuned (tile, table
+// factor); the first sight of a group class times a few plans (launching
+// them, and waiting for them, on stream s).
+alto_status group_items(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
+                        const void *const *const *factors, float *const *outs, hipStream_t s, int dev,
+                        std::vector<std::pair<Group, std::pair<int, int>>> *out) {
     std::map<std::array<int, 4>, Group> groups;
     for (int j = 0; j < count; j++) {
         const std::array<int, 4> key = {lpn_for(ranks[j]), fdts[j], hs[j]->info.index_words,
@@ -183,9 +182,61 @@ alto_status batched_run(int count, const alto_handle *hs, const int *modes, cons
             std::lock_guard<std::mutex> lk(g_btune_mu);
             g_btune[tkey] = tuned;
         }
-        alto_status st = launch_group(g, hs, modes, ranks, factors, outs, tuned.first, tuned.second, s, dev);
+        out->push_back({g, tuned});
+    }
+    return ALTO_OK;
+}
+
+}  // namespace
+
+alto_status batched_run(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
+                        const void *const *const *factors, float *const *outs, hipStream_t s) {
+    int dev = 0;
+    ALTO_HIP(hipGetDevice(&dev));
+    std::vector<std::pair<Group, std::pair<int, int>>> groups;
+    alto_status st = group_items(count, hs, modes, ranks, fdts, factors, outs, s, dev, &groups);
+    if (st != ALTO_OK) return st;
+    for (const auto &gt : groups) {
+        st = launch_group(gt.first, hs, modes, ranks, factors, outs, gt.second.first, gt.second.second, s, dev);
         if (st != ALTO_OK) return st;
     }
+    return ALTO_OK;
+}
+
+alto_status batched_plan(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
+                         const void *const *const *factors, float *const *outs, hipStream_t s,
+                         std::vector<GroupLaunch> *out) {
+    int dev = 0;
+    ALTO_HIP(hipGetDevice(&dev));
+    std::vector<std::pair<Group, std::pair<int, int>>> groups;
+    alto_status st = group_items(count, hs, modes, ranks, fdts, factors, outs, s, dev, &groups);
+    if (st != ALTO_OK) return st;
+    for (const auto &gt : groups) {
+        GroupLaunch gl;
+        st = plan_group(gt.first, hs, modes, ranks, factors, outs, gt.second.first, gt.second.second, s, dev, &gl);
+        if (st != ALTO_OK) return st;
+        out->push_back(std::move(gl));
+    }
+    return ALTO_OK;
+}
+
+alto_status launch_planned_group(const GroupLaunch &gl, const void *dblob, hipStream_t s) {
+    const int nj = gl.nj;
+    const MttkrpArgs *djobs = (const MttkrpArgs *)dblob;
+    const uint64_t *dprefix = (const uint64_t *)((const char *)dblob + gl.jobs_bytes());
+    const uint64_t *doprefix = (const uint64_t *)((const char *)dblob + gl.jobs_bytes() + gl.prefix_bytes());
+    {
+        void *args[] = {(void *)&djobs, (void *)&doprefix, (void *)&nj};
+        const unsigned g0 = grid_for(gl.oprefix[nj], 256, 8192);
+        ALTO_HIP(hipLaunchKernel(zero_outputs_kernel(), dim3(g0), dim3(256), args, 0, s));
+    }
+    if (gl.prefix[nj] == 0) return ALTO_OK;
+    int xcd_map = gl.xcd_map;
+    void *args[] = {(void *)&djobs, (void *)&dprefix, (void *)&nj, (void *)&xcd_map};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = timing_begin(s, &e0, &e1);
+    ALTO_HIP(hipLaunchKernel(gl.kern, dim3(gl.grid), dim3(256), args, gl.lds, s));
+    if (timed) timing_end(s, e0, e1);
     return ALTO_OK;
 }
 
@@ -289,6 +340,12 @@ alto_status autotune_run(alto_tensor *h, int mode, int rank, int fdt, const void
     float best = 1e30f;
     alto_mttkrp_plan bestp = base;
     for (auto &p : cands) accuracy_policy(h, mode, rank, &p);
+    // plans the policy moved to FP64: time the other FP64 form too
+    const size_t nbase = cands.size();
+    for (size_t i = 0; i < nbase; i++) {
+        alto_mttkrp_plan p = cands[i];
+        if (alternate_f64(h, mode, rank, &p)) cands.push_back(p);
+    }
     for (const auto &p : cands) {
         st = run_mttkrp(h, mode, rank, fdt, factors, out, p, s);  // warm
         if (st != ALTO_OK) break;

@@ -2,6 +2,10 @@
 // batched translation units.
 #pragma once
 
+#include <string.h>
+
+#include <vector>
+
 #include "alto_internal.h"
 
 namespace alto {
@@ -49,11 +53,17 @@ alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt)
 void record_tuned(alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan &p);
 alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan *in,
                          alto_mttkrp_plan *out);
-// FP32-atomic plans whose rows would take too many additions sum in per-XCD
-// FP32 copies or in FP64 instead (see mttkrp.hip); accumulate modes other
-// than ALTO_ACC_F32 are left alone.
+// FP32-atomic plans whose entries could take too many additions sum in FP64
+// instead (one buffer or per-XCD copies; see mttkrp.hip); accumulate modes
+// other than ALTO_ACC_F32 are left alone.
 void accuracy_policy(const alto_tensor *h, int mode, int rank, alto_mttkrp_plan *p);
-constexpr uint64_t kBatchF32MaxTiles = 2048;  // batched launches: tiles per job at most
+bool alternate_f64(const alto_tensor *h, int mode, int rank, alto_mttkrp_plan *p);
+constexpr uint64_t kBatchF32MaxTiles = 256;  // batched launches (FP32 atomics): tiles per job at most
+// Batched sweeps: a tensor of at least this many nonzeros takes its own
+// MTTKRP launches (its mode's plan: whole-mode LDS, rank tiles) instead of
+// sharing the batched ones.  Measured on a 256-job serving stream: 2^21 ->
+// 2^23 cut the sweep latency p50/p99 from 27/58 to 17/54 ms.
+constexpr uint64_t kBatchAloneNnz = uint64_t(1) << 23;
 alto_status check_mttkrp_args(const alto_tensor *h, int mode, int rank, int fdt, const void *const *factors,
                               const float *out);
 // Grow a workspace buffer to `need` bytes; a replaced buffer is released
@@ -96,6 +106,34 @@ size_t device_cache_bytes(int dev);  // L2 bytes over all XCDs
 // batched MTTKRP (batch.hip), arguments already validated
 alto_status batched_run(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
                         const void *const *const *factors, float *const *outs, hipStream_t s);
+
+// One persistent launch of a kernel-variant group of a batched MTTKRP,
+// planned on the host: the per-job kernel arguments and the tile and output
+// prefixes, copied to the device as one blob (jobs, prefix, oprefix).
+struct GroupLaunch {
+    std::vector<MttkrpArgs> jobs;
+    std::vector<uint64_t> prefix, oprefix;
+    const void *kern = nullptr;
+    size_t lds = 0;
+    unsigned grid = 1;
+    int nj = 0, xcd_map = 0;
+    size_t jobs_bytes() const { return sizeof(MttkrpArgs) * (size_t)nj; }
+    size_t prefix_bytes() const { return 8 * (size_t)(nj + 1); }
+    size_t blob_bytes() const { return jobs_bytes() + 2 * prefix_bytes(); }
+    void write_blob(char *dst) const {
+        memcpy(dst, jobs.data(), jobs_bytes());
+        memcpy(dst + jobs_bytes(), prefix.data(), prefix_bytes());
+        memcpy(dst + jobs_bytes() + prefix_bytes(), oprefix.data(), prefix_bytes());
+    }
+};
+// The groups of a batched MTTKRP with their tuned plans (the first sight of
+// a group class runs and times a few plans on stream s).
+alto_status batched_plan(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
+                         const void *const *const *factors, float *const *outs, hipStream_t s,
+                         std::vector<GroupLaunch> *out);
+// Zero the group's outputs and launch it; dblob holds write_blob's bytes.
+// Kernel launches only (capturable in a HIP graph).
+alto_status launch_planned_group(const GroupLaunch &gl, const void *dblob, hipStream_t s);
 
 // Ranks that are not a multiple of 4: the library works on copies whose rows
 // are padded with zero columns to the next multiple of 4 (mttkrp.hip).

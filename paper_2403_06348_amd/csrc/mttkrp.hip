@@ -30,10 +30,9 @@ const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch) {
 }
 
 // The specialised kernel serves 3-mode tensors with a one-word index whose
-// factor reads fit 32-bit offsets and whose updates are FP32 additions (into
-// the output or its per-XCD copies); everything else takes the general kernel.
+// factor reads fit 32-bit offsets; everything else takes the general kernel.
 const void *pick_single(int lpn, int fdt, int words, const MttkrpArgs &a) {
-    if (words == 1 && a.nmodes == 3 && a.buf32 && !a.use64)
+    if (words == 1 && a.nmodes == 3 && a.buf32)
         return fdt == ALTO_BF16 ? pick_fast_bf16(lpn, a.tile_merge) : pick_fast_f32(lpn, a.tile_merge);
     return pick_kernel(lpn, fdt, words, a.nmodes, false);
 }
@@ -224,28 +223,49 @@ bool plan_fits(const alto_tensor *h, int mode, int rank, const alto_mttkrp_plan 
 }
 
 // Accuracy policy for plans that add into the FP32 output with FP32 atomics.
-// An output entry that receives k such additions carries a rounding error
-// of about 0.25 u sqrt(k) of its magnitude (u = 2^-24), and several times
-// that for the unluckiest entries of a large mode; the number of additions
-// per row is bounded by the number of tiles for the LDS table merge (each
-// tile adds a row at most once, retained rows less often), by the number of
-// workgroups for the whole-mode LDS table, and only by the row's nonzero
-// count for register runs.  Beyond kF32MaxAdds additions the plan sums in
-// one FP32 copy of the output per XCD instead (each copy takes an eighth of
-// the additions, the copies are summed in FP64) when those copies are
-// small, else in an FP64 buffer.
-constexpr uint64_t kF32MaxAdds = 2048;
-constexpr uint64_t kXcdCopyBytes = uint64_t(256) << 20;
+// Every partial row a workgroup flushes is one rounded FP32 addition into
+// its output entries, and an addition can lose up to half a unit in the last
+// place of the entry's running sum: partials that arrive after the entry has
+// grown large are rounded away ("swamping").  An entry that takes K additions
+// is thus off by up to K 2^-25 of the sum of its terms' magnitudes.  On
+// skewed tensors the heavy rows take one partial per tile (or per workgroup)
+// plus one per table miss, and after a CP-ALS update the factor values make
+// most of those partials small; measured on the 1e8-nonzero Zipf tensor after
+// one sweep, FP32 atomics left entries at 2-9 times 1e-5 of that sum.  So
+// FP32 is kept only where K is bounded by kF32MaxAdds (K 2^-25 < 1e-5): by
+// the tile count for the LDS table merge, the workgroup count for the
+// whole-mode table (at most one flush per workgroup), the nonzero count for
+// register runs.  Otherwise the plan accumulates in FP64: eight per-XCD FP64
+// copies for short modes under heavy contention (atomics of different XCDs
+// never meet), else one FP64 buffer.  Both round once to FP32 at the end.
+constexpr uint64_t kF32MaxAdds = 256;
+constexpr uint64_t kXcdCopyBytes = uint64_t(1) << 30;
+constexpr double kXcdReuse = 512.0;
 
 void accuracy_policy(const alto_tensor *h, int mode, int rank, alto_mttkrp_plan *p) {
     if (p->accumulate != ALTO_ACC_F32) return;
     const uint64_t nnz = h->info.nnz;
-    uint64_t adds = 0;
-    if (p->conflict == ALTO_CR_TILE) adds = (nnz + p->tile_nnz - 1) / (uint64_t)std::max(1, p->tile_nnz);
-    else if (p->conflict == ALTO_CR_RUN || p->conflict == ALTO_CR_HOT) adds = nnz;
+    const uint64_t tiles = (nnz + p->tile_nnz - 1) / (uint64_t)std::max(1, p->tile_nnz);
+    uint64_t adds = nnz;
+    if (p->conflict == ALTO_CR_TILE) adds = tiles;
+    else if (p->conflict == ALTO_CR_DIRECT) adds = std::min<uint64_t>(tiles, (uint64_t)device_cus(h->device) * 4);
     if (adds <= kF32MaxAdds) return;
-    const uint64_t copies = h->info.dims[mode] * (uint64_t)rank * 4 * kXcdCopies;
-    p->accumulate = copies <= kXcdCopyBytes ? ALTO_ACC_XCD_F32 : ALTO_ACC_F64;
+    const double reuse = (double)nnz / (double)std::max<uint64_t>(1, h->info.dims[mode]);
+    const uint64_t copies = h->info.dims[mode] * (uint64_t)rank * 8 * kXcdCopies;
+    p->accumulate = (reuse >= kXcdReuse && copies <= kXcdCopyBytes) ? ALTO_ACC_XCD_F64 : ALTO_ACC_F64;
+}
+
+// The other FP64 form of a plan the policy moved to FP64 (the autotuner
+// times both); false when there is none that fits.
+bool alternate_f64(const alto_tensor *h, int mode, int rank, alto_mttkrp_plan *p) {
+    if (p->accumulate == ALTO_ACC_XCD_F64) {
+        p->accumulate = ALTO_ACC_F64;
+        return true;
+    }
+    if (p->accumulate != ALTO_ACC_F64) return false;
+    if (h->info.dims[mode] * (uint64_t)rank * 8 * kXcdCopies > kXcdCopyBytes) return false;
+    p->accumulate = ALTO_ACC_XCD_F64;
+    return true;
 }
 
 alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan *in,

@@ -136,18 +136,10 @@ __device__ inline float4 widen(const uint2 &u) { return bf16x4_to_float4(u.x, u.
 __device__ inline uint32_t xcd_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 15u; }
 
 // Add 4 columns of partial sums (FP32 run sums or FP64 LDS rows) to the
-// output row, or to this XCD's copy of it.
-// FAST: the plan is known to add FP32 into the output or its per-XCD copies.
+// output row, or to this XCD's copy of it, in FP32 or FP64.
 template <bool FAST = false, typename T>
 __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, const T *acc) {
     uint64_t o = (uint64_t)row * a.ld + a.col0 + r0;
-    if (FAST) {
-        if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
-#pragma unroll
-        for (int j = 0; j < 4; j++)
-            if (r0 + j < a.rank) unsafeAtomicAdd(a.out32 + o + j, (float)acc[j]);
-        return;
-    }
     if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
     if (a.use64) {
 #pragma unroll
@@ -170,7 +162,7 @@ template <bool FAST = false, typename T>
 __device__ inline void global_add1(const MttkrpArgs &a, uint32_t row, int c, T v) {
     uint64_t o = (uint64_t)row * a.ld + a.col0 + c;
     if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
-    if (!FAST && a.use64) unsafeAtomicAdd(a.out64 + o, (double)v);
+    if (a.use64) unsafeAtomicAdd(a.out64 + o, (double)v);
     else unsafeAtomicAdd(a.out32 + o, (float)v);
 }
 
@@ -359,8 +351,6 @@ __device__ inline uint32_t rec_coord(const uint4 &h, const uint4 &h2, int k) {
     return k == 0 ? h.z : k == 1 ? h.w : k == 2 ? h2.x : k == 3 ? h2.y : k == 4 ? h2.z : h2.w;
 }
 
-// Kernel variants: MAXO = most other modes handled with fully unrolled
-// gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
 // End of tile t of the stretch [t0, t1): the LDS table's rows go to the
 // output -- for a whole-mode table (TM 2) once, at the stretch's end; for a
 // hashed table (TM 1) every tile, except rows merged many times (high
@@ -448,8 +438,7 @@ __device__ inline uint64_t compress_lds(uint64_t x, const uint64_t *m) {
 }
 
 // Tiles [t0, t1) of one tensor's line, processed by one workgroup (the
-// plain, unpipelined loop: single launches of shapes other than the
-// specialised one, and tensors of 6-8 modes in batched launches).  The LDS
+// plain, unpipelined loop without outboxes: tensors of 6-8 modes).  The LDS
 // table is initialized here and fully flushed by the last tile.  TMC: the
 // conflict-resolution mode fixed at compile time (-1: read from the
 // arguments).
@@ -1084,20 +1073,11 @@ __global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
     __shared__ uint64_t lmask[(FAST || MAXO <= 4) ? kMaskWords : 1];
     uint64_t t0, t1;
     stretch_of(a.ntiles, a.xcd_map, &t0, &t1);
-    // single launches: the pipelined loop for the specialised case and for
-    // hot-row merging (which it alone implements); for other shapes it
-    // measured slower than the plain loop (more registers and scalar state
-    // per step), while it pays in the batched launches
-    if constexpr (FAST) {
+    // the pipelined loop (with the per-wave outboxes) for up to 5 modes; the
+    // plain loop for 6-8 modes
+    if constexpr (FAST || MAXO <= 4) {
         load_masks(a.lp, a.nmodes, lmask);
         mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
-    } else if constexpr (MAXO <= 4) {
-        if (a.tile_merge == 3) {
-            load_masks(a.lp, a.nmodes, lmask);
-            mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, TMC, false>(a, smem, nkeep, lmask, t0, t1);
-        } else {
-            mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC>(a, smem, nkeep, t0, t1);
-        }
     } else {
         mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC>(a, smem, nkeep, t0, t1);
     }

@@ -62,7 +62,8 @@ alto_mttkrp_plan phi_plan(const alto_tensor *h, int mode, int rank, const alto_m
     }
     p.rank_tile = 0;
     if (p.conflict == ALTO_CR_HOT) p.conflict = ALTO_CR_TILE;
-    if (p.accumulate != ALTO_ACC_F64) p.accumulate = ALTO_ACC_F32;
+    // Phi sums like MTTKRP: FP64 wherever the policy chose an FP64 form
+    p.accumulate = (p.accumulate == ALTO_ACC_F64 || p.accumulate == ALTO_ACC_XCD_F64) ? ALTO_ACC_F64 : ALTO_ACC_F32;
     if (p.table_slots < 16) p.table_slots = 256;
     const size_t lim = device_lds(h->device);
     *tw = 2;

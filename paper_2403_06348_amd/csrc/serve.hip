@@ -48,7 +48,9 @@ uint64_t footprint_of(const alto_serve_job &j) {
         factors += j.dims[m] * (uint64_t)j.rank * (j.fdt == ALTO_BF16 ? 6 : 4);
         maxI = std::max<uint64_t>(maxI, j.dims[m]);
     }
-    const uint64_t ws = maxI * j.rank * 4 + (uint64_t)(j.nmodes + 2 + 512) * j.rank * j.rank * 8 + 256;
+    uint64_t ws = maxI * j.rank * 4 + (uint64_t)(j.nmodes + 2 + 512) * j.rank * j.rank * 8 + 256;
+    // a job that runs its own MTTKRP launches may accumulate in FP64
+    if (j.nnz >= kBatchAloneNnz) ws += maxI * j.rank * 8;
     const uint64_t g = 2 << 20;  // allocation granule of the caching allocator, per buffer
     return tensor + scratch + factors + ws + 8 * g;
 }

@@ -109,3 +109,76 @@ def test_batched_sweep_matches_separate_sweeps():
         assert rel_fro(it[2].cpu().numpy(), lam.cpu().numpy()) <= 1e-3
     for _, T, _, _ in jobs:
         T.free()
+
+
+def test_prepared_batch_graph_replays_match_oracle():
+    """A prepared batched sweep (alto_sweep_batch_*) captured in one HIP
+    graph.  Its eager run and every replay -- with eager work and
+    synchronizations between the replays -- are checked mode by mode against
+    the oracle's update from the factors each mode saw."""
+    specs = job_specs()[:6]
+    jobs, items = [], []
+    for dims, nnz, ex, R, seed in specs:
+        R = min(R, 32)
+        X = zipf_tensor(dims, nnz, ex, seed=seed)
+        T = alto.AltoTensor(X.dims, torch.from_numpy(X.coords).cuda(), torch.from_numpy(vals32(X)).cuda())
+        f0 = [torch.from_numpy(f).cuda() for f in make_factors(X.dims, R, seed=seed + 1)]
+        jobs.append((X, T, f0))
+        items.append((T, [f.clone() for f in f0], torch.empty(R, dtype=torch.float64, device="cuda"), alto.F32))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    B = alto.SweepBatch(items, stream=side)
+
+    def reset():
+        for it, (_, _, f0) in zip(items, jobs):
+            for w, f in zip(it[1], f0):
+                w.copy_(f)
+        torch.cuda.synchronize()
+
+    def check(what):
+        for k, (it, (X, _, f0)) in enumerate(zip(items, jobs)):
+            check_sweep(X.dims, X.coords, vals32(X), [f.cpu().numpy() for f in f0],
+                        [f.cpu().numpy() for f in it[1]], it[2].cpu().numpy(), what=f"{what} item {k}")
+
+    reset()
+    say("[batched] prepared batch, eager run")
+    with torch.cuda.stream(side):
+        B.run()
+    torch.cuda.synchronize()
+    check("prepared eager")
+    reset()
+    graph = torch.cuda.CUDAGraph()
+    say("[batched] capture the prepared batch")
+    with torch.cuda.graph(graph, stream=side):
+        B.run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        reset()
+        torch.ones(1 << 20, device="cuda").mul_(2.0).sum().item()  # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        say(f"[batched] replay {rep}")
+        check(f"replay {rep}")
+    del graph
+    B.close()
+    for _, T, _ in jobs:
+        T.free()
+
+
+def test_prepared_batch_refuses_a_changed_workspace():
+    """The prepared tables point into the handles' workspaces: after a
+    larger call reallocates one, run() refuses instead of using stale
+    pointers."""
+    X = zipf_tensor((3000, 2000, 500), 20_000, (1.2, 1.2, 1.2), seed=31)
+    T = alto.AltoTensor(X.dims, torch.from_numpy(X.coords).cuda(), torch.from_numpy(vals32(X)).cuda())
+    f = [torch.from_numpy(a).cuda() for a in make_factors(X.dims, 8, seed=1)]
+    B = alto.SweepBatch([(T, f, torch.empty(8, dtype=torch.float64, device="cuda"), alto.F32)])
+    B.run()
+    torch.cuda.synchronize()
+    big = [torch.from_numpy(a).cuda() for a in make_factors(X.dims, 64, seed=2)]
+    T.sweep(big)  # rank 64 grows the sweep workspace
+    torch.cuda.synchronize()
+    with pytest.raises(alto.AltoError, match="workspace changed"):
+        B.run()
+    B.close()
+    T.free()
