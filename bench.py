@@ -320,6 +320,60 @@ def precision_report(T, X, coords, vals, facs0, rank, nsweeps, torch, alto, nrow
             "fp64_reference": "float64 tensor ops on the GPU over the nonzeros of the sampled rows, BF16-rounded factors"}
 
 
+def batch_graph_leg(alto, torch, njobs=32, nnz_hi=2e6, seed=9):
+    """One CP-ALS sweep of every job of a serving-like batch (3-5 modes,
+    dims log-uniform [1e3,1e6], nnz log-uniform [1e4,nnz_hi], R in {8,16,32}):
+    the eager batched call, the prepared batch's run, and that run captured
+    once in a HIP graph and replayed.  Median of 5 each (HIP events)."""
+    import numpy as np
+
+    from synth.serving import job_stream, make_job_tensors
+
+    jobs = job_stream(count=njobs, seed=seed, nnz_hi=nnz_hi)
+    items, hold = [], []
+    for j in jobs:
+        coords, vals, facs = make_job_tensors(j)
+        T = alto.AltoTensor(j.dims, torch.stack(coords), vals)
+        hold.append(T)
+        items.append((T, facs, torch.empty(j.rank, dtype=torch.float64, device="cuda"), alto.F32))
+    work = sum(j.nnz * len(j.dims) for j in jobs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def med(fn):
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            with torch.cuda.stream(side):
+                ev[0].record()
+                fn()
+                ev[1].record()
+            torch.cuda.synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]))
+        return float(np.median(ts))
+
+    eager_ms = med(lambda: alto.sweep_batched(items))
+    B = alto.SweepBatch(items, stream=side)
+    prepared_ms = med(B.run)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        B.run()
+    torch.cuda.synchronize()
+    graph_ms = med(graph.replay)
+    del graph
+    B.close()
+    for T in hold:
+        T.free()
+    return {"jobs": njobs, "nnz_total": int(sum(j.nnz for j in jobs)), "eager_ms": round(eager_ms, 3),
+            "prepared_ms": round(prepared_ms, 3), "graph_replay_ms": round(graph_ms, 3),
+            "graph_gnnz_s": round(work / (graph_ms * 1e-3) / 1e9, 3),
+            "workload": f"one CP-ALS sweep of {njobs} jobs, 3-5 modes, dims log-uniform [1e3,1e6], nnz log-uniform "
+                        f"[1e4,{nnz_hi:g}], Zipf(1.2), R in {{8,16,32}}"}
+
+
 def serving_run(njobs, nnz_hi, sweeps, load, budget_gb, max_active, seed=5):
     """The continuous-batching server on a Poisson stream of CP-ALS jobs.
     Returns a dict with sweep-latency percentiles and aggregate throughput."""
@@ -382,6 +436,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-parallel", action="store_true")
     ap.add_argument("--no-phi", action="store_true", help="skip the CP-APR Phi leg")
+    ap.add_argument("--no-batch-graph", action="store_true", help="skip the batched-sweep graph leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default=None, help="JSON MTTKRP plan override")
     ap.add_argument("--no-autotune", action="store_true")
@@ -642,6 +697,9 @@ def main():
     }
     if precision:
         out["precision_form"] = precision
+    if not args.no_batch_graph:
+        log("[bench] batched sweep: eager, prepared, graph replay")
+        out["batched_sweep"] = batch_graph_leg(alto, torch)
     if args.serve_jobs > 0:
         del coords, vals
         torch.cuda.empty_cache()
