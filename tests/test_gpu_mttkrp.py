@@ -150,6 +150,41 @@ def test_autotune_records_a_plan_and_stays_exact():
     T2.free()
 
 
+def test_cached_plan_that_does_not_fit_falls_back():
+    """The process-wide tuned-plan cache is keyed by a tensor class, within
+    which a mode's length can differ by 4x.  A whole-mode-in-LDS plan tuned
+    on a 520-row mode must not be used for a 2047-row mode of the same class
+    (it would not fit the LDS): a plain call with no plan falls back to the
+    default plan and stays exact."""
+    from synth import zipf_tensor
+
+    R = 32
+    # same class: 3 modes, one index word, R=32, floor(log2 nnz) = 20 and
+    # floor(log2 reuse of mode 2) = 10; mode 2 of B is 3.9x longer than A's
+    A = zipf_tensor((3000, 2500, 520), 1 << 20, (1.2, 1.2, None), seed=41, name="classA")
+    B = zipf_tensor((3000, 2500, 2047), (1 << 21) - 1, (1.2, 1.2, None), seed=42, name="classB")
+    TA = alto.AltoTensor(A.dims, *upload(A))
+    fa = [torch.from_numpy(f).cuda() for f in factors_for(A, R, seed=5)]
+    chosen = TA.autotune(2, fa, out=torch.empty((A.dims[2], R), device="cuda"))
+    say(f"[mttkrp] class A mode 2 tuned plan {chosen}")
+    TB = alto.AltoTensor(B.dims, *upload(B))
+    facs = factors_for(B, R, seed=6)
+    fb = [torch.from_numpy(f).cuda() for f in facs]
+    got = TB.mttkrp(2, fb).cpu().numpy().astype(np.float64)  # no plan: cache, else default
+    pb = TB.get_plan(2, R)
+    say(f"[mttkrp] class B mode 2 plan {pb}")
+    if chosen["conflict"] == alto.CR_DIRECT:
+        assert pb["conflict"] != alto.CR_DIRECT or pb["rank_tile"] not in (0, R)
+    v64 = vals32(B).astype(np.float64)
+    f64 = [f.astype(np.float64) for f in facs]
+    ref = oracle.mttkrp(B.dims, B.coords, v64, f64, 2)
+    S = oracle.mttkrp_abs(B.dims, B.coords, v64, f64, 2)
+    assert rel_fro(got, ref) <= 1e-5
+    assert_entrywise(got, ref, S, what="class B mode 2")
+    TA.free()
+    TB.free()
+
+
 def test_mttkrp_graph_capture_replays_match_eager():
     """MTTKRP of every mode captured in one HIP graph; each replay, with eager
     work between replays, matches the eager result."""
