@@ -269,6 +269,35 @@ def phi_leg(T, X, facs, rank, words, ev):
     return res
 
 
+def cpapr_leg(T, X, rank, torch, ev, l_max=10):
+    """One outer iteration of CP-APR by multiplicative updates (every mode,
+    l_max inner iterations each: the KKT tolerance is set to 0 so that no
+    mode stops early) from positive factors and unit weights, with Pi rows
+    precomputed per mode (ALTO-PRE) and formed on the fly (ALTO-OTF), timed
+    with HIP events around the whole call (it synchronizes once per inner
+    iteration to read the KKT value).  The library's rule picks PRE for
+    4-mode and larger tensors at l_max >= 5 (Pi up to 32 GiB)."""
+    from synth import make_factors
+
+    res = {"rank": rank, "l_max": l_max, "library_form": "pre" if X.nmodes >= 4 else "otf"}
+    for name, form in (("pre", 1), ("otf", 2)):
+        facs = [torch.from_numpy(0.1 + f).cuda() for f in make_factors(X.dims, rank, seed=3)]
+        lam = torch.ones(rank, dtype=torch.float64, device="cuda")
+        T.cpapr_mu([f.clone() for f in facs], lam.clone(), k_max=1, l_max=1, tau=0.0, pi_form=form)  # workspace
+        torch.cuda.synchronize()
+        ev[0].record()
+        k, counts, _ = T.cpapr_mu(facs, lam, k_max=1, l_max=l_max, tau=0.0, pi_form=form)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        evals = sum(sum(c) for c in counts)
+        res[name] = {"outer_ms": round(ms, 3), "phi_evaluations": evals, "ms_per_phi_evaluation": round(ms / evals, 4),
+                     "gnnz_s": round(X.nnz * evals / (ms * 1e-3) / 1e9, 3)}
+        del facs, lam
+        torch.cuda.empty_cache()
+    return res
+
+
 def precision_report(T, X, coords, vals, facs0, rank, nsweeps, torch, alto, nrows=64, seed=40):
     """The precision form over a whole run: ``nsweeps`` CP-ALS sweeps with
     BF16 factor shadows.  Each MTTKRP of each sweep is redone from the inputs
@@ -622,6 +651,9 @@ def main():
             bf16_err.append(float((ob - of).norm() / of.norm()))
             del ob, of
     phi = None if args.no_phi else phi_leg(T, X, facs0, rank, info_words, ev)
+    if phi is not None and X.nmodes <= 5:
+        log("[bench] CP-APR multiplicative updates, one outer iteration")
+        phi["mu_outer_iteration"] = cpapr_leg(T, X, rank, torch, ev)
     precision = precision_report(T, X, coords, vals, facs0, rank, nsweeps, torch, alto) if fdt == alto.BF16 else None
     T.free()
     torch.cuda.synchronize()

@@ -402,6 +402,46 @@ alto_status cpd_als(alto_handle h, int rank, alto_dtype fdt, float *const *facto
  */
 alto_status alto_sweep_flags(alto_handle h, void *stream, uint32_t *flags /*host*/);
 
+/*
+ * CP-APR by multiplicative updates (Algorithm "alg:cp-apr-mu"), around the
+ * Phi and Pi kernels above.  For each outer iteration k <= k_max and mode n:
+ * S = kappa where k > 1, A^(n) < kappa_tol and the mode's last Phi exceeds 1
+ * (else 0); B = (A^(n) + S) Lambda; then up to l_max inner iterations of
+ * Phi = (X_(n) ./ max(B Pi, eps)) Pi^T, stopping when the KKT violation
+ * max over entries of |min(B, 1 - Phi)| is below tau, else B = B * Phi;
+ * finally lambda = the column sums of B and A^(n) = B Lambda^-1 (a zero
+ * column stays zero).  The outer loop ends early when no mode needed an
+ * update (*converged = 1).  Pi rows are precomputed per mode and outer
+ * iteration (nnz x rank FP32 of handle workspace) where alto_cpapr_prefer_pre
+ * says so, and also for tensors of 4 or more modes when l_max >= 5 and Pi
+ * takes at most 32 GiB: one streamed Pi row per nonzero then replaces N-1
+ * gathered factor rows in every inner iteration (measured on the 4-mode
+ * 2e8-nonzero workload at rank 32: Phi 11.7-26.6 ms from Pi against
+ * 17.0-26.5 ms on the fly, Pi 12.6 ms per mode); else Pi rows are formed on
+ * the fly.  params->pi_form overrides the rule.
+ * factors (host array of device FP32 dims[m] x rank, non-negative) and
+ * lambda (device FP64 [rank]; the caller's initial weights, e.g. ones) are
+ * updated in place.  rank a multiple of 4 in 4..128; up to 5 modes.
+ * outer_done, inner_counts (host [k_max x nmodes]: Phi evaluations per outer
+ * iteration and mode) and converged may be NULL.  Blocking: synchronizes the
+ * stream once per inner iteration to read the KKT value.  B and Phi are FP32,
+ * lambda and the reductions FP64.  Errors: ALTO_ERR_ARG for bad arguments.
+ */
+typedef struct {
+    int k_max;         /* outer iterations at most                           */
+    int l_max;         /* inner iterations per mode at most (10 in the paper) */
+    double tau;        /* KKT tolerance                                      */
+    double kappa;      /* inadmissible-zero adjustment                       */
+    double kappa_tol;  /* factor entries below this may be inadmissible zeros */
+    float eps;         /* divisor floor of Phi                               */
+    int pi_form;       /* 0: the library's rule (below), 1: Pi precomputed   */
+                       /* per mode and outer iteration (ALTO-PRE), 2: Pi rows */
+                       /* formed on the fly (ALTO-OTF)                        */
+} alto_cpapr_params;
+alto_status alto_cpapr_mu(alto_handle h, int rank, float *const *factors /*host[N] of device ptrs*/,
+                          double *lambda, const alto_cpapr_params *params /*host*/, int *outer_done /*host*/,
+                          int *inner_counts /*host*/, int *converged /*host*/, void *stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /*

@@ -384,3 +384,72 @@ def cp_als(dims, coords, vals, factors, max_sweeps: int, tol: float):
         if len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
             break
     return A, lam, fits
+
+
+def poisson_objective(dims, coords, vals, factors, lam) -> float:
+    """Negative Poisson log-likelihood of the model [lam; A^(0..N-1)] for the
+    count tensor the nonzeros add up to, up to the constant sum(log x!):
+    sum over all entries of the model minus sum over the nonzeros of
+    x log(model).  The model's total is sum_r lam_r prod_m (column sum of
+    A^(m)(:, r)).  Duplicate coordinates are summed first."""
+    c = np.ascontiguousarray(coords, dtype=np.int64)
+    v = np.asarray(vals, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    total = float(np.sum(lam * np.prod([np.asarray(f, dtype=np.float64).sum(axis=0) for f in factors], axis=0)))
+    if c.shape[1] == 0:
+        return total
+    flat = np.ravel_multi_index(tuple(c), tuple(int(d) for d in dims))
+    cells, inv = np.unique(flat, return_inverse=True)
+    x = np.bincount(inv, weights=v)
+    first = np.zeros(len(cells), dtype=np.int64)
+    first[inv[::-1]] = np.arange(c.shape[1])[::-1]
+    model = np.ones((len(cells), lam.shape[0])) * lam[None, :]
+    for m, f in enumerate(factors):
+        model *= np.asarray(f, dtype=np.float64)[c[m, first]]
+    mv = model.sum(axis=1)
+    return total - float(np.sum(x * np.log(mv)))
+
+
+def cp_apr_mu(dims, coords, vals, factors, lam=None, k_max: int = 10, l_max: int = 10, tau: float = 1e-4,
+              kappa: float = 1e-2, kappa_tol: float = 1e-10, eps: float = 1e-10):
+    """Algorithm "alg:cp-apr-mu" (CP-APR by multiplicative updates) in FP64,
+    step by step: for each outer iteration k and mode n, S (the
+    inadmissible-zero adjustment: kappa where k > 1, A^(n) < kappa_tol and the
+    mode's last Phi exceeds 1), B = (A^(n) + S) Lambda, then up to l_max
+    inner iterations of Phi (``phi``, the Pi rows formed on the fly), the KKT
+    check max|min(B, 1 - Phi)| < tau, and B = B * Phi; finally lambda = the
+    column sums of B and A^(n) = B Lambda^-1 (a zero column stays zero).  The
+    outer loop stops early when no mode needed an update.  lam defaults to
+    ones.  Returns (factors, lam, outer iterations run, inner iterations per
+    outer iteration and mode, converged)."""
+    A = [np.array(f, dtype=np.float64, copy=True) for f in factors]
+    N = len(A)
+    R = A[0].shape[1]
+    lam = np.ones(R) if lam is None else np.array(lam, dtype=np.float64, copy=True)
+    last_phi = [None] * N
+    inner = []
+    converged = False
+    k = 0
+    for k in range(1, k_max + 1):
+        converged = True
+        counts = []
+        for n in range(N):
+            S = np.zeros_like(A[n])
+            if k > 1:
+                S[(A[n] < kappa_tol) & (last_phi[n] > 1.0)] = kappa
+            B = (A[n] + S) * lam[None, :]
+            runs = 0
+            for _ in range(l_max):
+                last_phi[n] = phi(dims, coords, vals, A, B, n, eps)
+                runs += 1
+                if np.max(np.abs(np.minimum(B, 1.0 - last_phi[n]))) < tau:
+                    break
+                converged = False
+                B = B * last_phi[n]
+            lam = B.sum(axis=0)
+            A[n] = B / np.where(lam > 0, lam, 1.0)[None, :]
+            counts.append(runs)
+        inner.append(counts)
+        if converged:
+            break
+    return A, lam, k, inner, converged

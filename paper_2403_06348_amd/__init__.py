@@ -248,6 +248,32 @@ class AltoTensor:
                "alto_cpapr_phi")
         return out
 
+    def cpapr_mu(self, factors, lam, k_max=10, l_max=10, tau=1e-4, kappa=1e-2, kappa_tol=1e-10, eps=1e-10,
+                 pi_form=0, stream=None):
+        """CP-APR by multiplicative updates (alto_cpapr_mu): ``factors``
+        (non-negative FP32 CUDA tensors) and ``lam`` (FP64 CUDA tensor, the
+        initial weights) are updated in place.  pi_form: 0 the library's
+        rule, 1 precomputed Pi (ALTO-PRE), 2 on the fly (ALTO-OTF).  Returns (outer iterations,
+        Phi evaluations per outer iteration and mode, converged)."""
+        n = self.nmodes
+        rank = int(factors[0].shape[1])
+        torch = _torch()
+        for m, f in enumerate(factors):
+            if f.dtype != torch.float32 or not f.is_cuda or not f.is_contiguous() or tuple(f.shape) != (self.dims[m], rank):
+                raise ValueError(f"factors[{m}] must be a contiguous float32 CUDA tensor of shape ({self.dims[m]}, {rank})")
+        if lam.dtype != torch.float64 or not lam.is_cuda or lam.numel() != rank:
+            raise ValueError(f"lam must be a float64 CUDA tensor of {rank} entries")
+        farr = _factor_array(factors, n)
+        prm = _capi.CpaprParams(int(k_max), int(l_max), float(tau), float(kappa), float(kappa_tol), float(eps),
+                                int(pi_form))
+        outer = ctypes.c_int(0)
+        conv = ctypes.c_int(0)
+        counts = (ctypes.c_int * (int(k_max) * n))()
+        _check(_capi.lib().alto_cpapr_mu(self.handle, rank, farr, _ptr(lam), ctypes.byref(prm), ctypes.byref(outer),
+                                         counts, ctypes.byref(conv), _stream(stream)), "alto_cpapr_mu")
+        k = outer.value
+        return k, [[counts[i * n + m] for m in range(n)] for i in range(k)], bool(conv.value)
+
     def get_plan(self, mode: int, rank: int, fdt=F32) -> dict:
         p = MttkrpPlan()
         _check(_capi.lib().alto_mttkrp_get_plan(self.handle, int(mode), int(rank), int(fdt), ctypes.byref(p)),

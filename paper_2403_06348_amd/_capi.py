@@ -56,6 +56,18 @@ class MttkrpPlan(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class CpaprParams(ctypes.Structure):
+    _fields_ = [
+        ("k_max", ctypes.c_int),
+        ("l_max", ctypes.c_int),
+        ("tau", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("kappa_tol", ctypes.c_double),
+        ("eps", ctypes.c_float),
+        ("pi_form", ctypes.c_int),
+    ]
+
+
 class Info(ctypes.Structure):
     _fields_ = [
         ("nmodes", ctypes.c_int),
@@ -156,6 +168,8 @@ SIGNATURES = {
     "cpd_als": (I32, [P, I32, I32, P, P, I32, ctypes.c_double, P, ctypes.POINTER(I32), P]),
     "cpd_als_sweep_batched": (I32, [I32, P, P, P, P, P, P]),
     "alto_sweep_batch_create": (I32, [I32, P, P, P, P, P, P, ctypes.POINTER(P)]),
+    "alto_cpapr_mu": (I32, [P, I32, P, P, ctypes.POINTER(CpaprParams), ctypes.POINTER(I32), P,
+                            ctypes.POINTER(I32), P]),
     "alto_sweep_batch_run": (I32, [P, P]),
     "alto_sweep_batch_destroy": (I32, [P]),
     "alto_server_create": (I32, [U64, I32, ctypes.POINTER(P)]),

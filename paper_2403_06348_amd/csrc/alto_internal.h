@@ -103,6 +103,15 @@ struct alto_tensor {
     double *ws_fit;        // fit: [0] = ||X||^2 of the summed tensor, [1] = last fit (device)
     size_t ws_fit_bytes;
     bool xnorm_ready;      // ws_fit[0] holds ||X||^2
+    // CP-APR: each mode's last Phi, the B iterates, reductions, Pi rows
+    float *ws_apr_phi[ALTO_MAX_MODES];
+    size_t ws_apr_phi_bytes[ALTO_MAX_MODES];
+    float *ws_apr_b;
+    size_t ws_apr_b_bytes;
+    double *ws_apr_red;
+    size_t ws_apr_red_bytes;
+    float *ws_apr_pi;
+    size_t ws_apr_pi_bytes;
     // per (mode, rank, dtype) tuned plans
     alto_mttkrp_plan tuned[ALTO_MAX_MODES][2][33];
     bool has_tuned[ALTO_MAX_MODES][2][33];

@@ -602,6 +602,10 @@ alto_status alto_free(alto_handle h) {
     dev_free_after(h->ws_lampad, s);
     for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free_after(h->ws_pad[n], s);
     for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free_after(h->ws_bf16[n], s);
+    for (int n = 0; n < ALTO_MAX_MODES; n++) dev_free_after(h->ws_apr_phi[n], s);
+    dev_free_after(h->ws_apr_b, s);
+    dev_free_after(h->ws_apr_red, s);
+    dev_free_after(h->ws_apr_pi, s);
     h->magic = 0;
     delete h;
     return ALTO_OK;

@@ -135,6 +135,14 @@ alto_status batched_plan(int count, const alto_handle *hs, const int *modes, con
 // Kernel launches only (capturable in a HIP graph).
 alto_status launch_planned_group(const GroupLaunch &gl, const void *dblob, hipStream_t s);
 
+// CP-APR (phi.hip): Phi of a mode into `phi` (dims[mode] x rank FP32) from
+// B and the other factors, or from precomputed Pi rows (ALTO order); Pi rows
+// of a mode; whether the PRE form is the better one for a mode.
+alto_status run_phi(alto_tensor *h, int mode, int rank, const void *const *factors, const float *B, float eps,
+                    const float *pi, float *phi, const alto_mttkrp_plan *in, hipStream_t s);
+alto_status run_pi(alto_tensor *h, int mode, int rank, const float *const *factors, float *pi, hipStream_t s);
+bool prefer_pre(const alto_tensor *h, int mode, int rank);
+
 // Ranks that are not a multiple of 4: the library works on copies whose rows
 // are padded with zero columns to the next multiple of 4 (mttkrp.hip).
 inline int padded_rank(int rank) { return (rank + 3) & ~3; }

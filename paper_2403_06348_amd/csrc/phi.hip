@@ -78,6 +78,8 @@ alto_mttkrp_plan phi_plan(const alto_tensor *h, int mode, int rank, const alto_m
     return p;
 }
 
+}  // namespace
+
 alto_status run_phi(alto_tensor *h, int mode, int rank, const void *const *factors, const float *B, float eps,
                     const float *pi, float *phi, const alto_mttkrp_plan *in, hipStream_t s) {
     h->stream = s;
@@ -116,19 +118,19 @@ alto_status run_phi(alto_tensor *h, int mode, int rank, const void *const *facto
     return ALTO_OK;
 }
 
-}  // namespace
-}  // namespace alto
+// ALTO-PRE when fiber reuse is low (the conflict-resolution rule's
+// threshold) and the other modes' factor matrices are well beyond the
+// on-chip cache (Sec. "Adaptive Memory Management").
+bool prefer_pre(const alto_tensor *h, int mode, int rank) {
+    const double reuse = (double)h->info.nnz / (double)h->info.dims[mode];
+    uint64_t fbytes = 0;
+    for (int m = 0; m < h->info.nmodes; m++)
+        if (m != mode) fbytes += h->info.dims[m] * (uint64_t)rank * 4;
+    return reuse <= 4.0 && fbytes > 2 * device_cache_bytes(h->device);
+}
 
-using namespace alto;
-
-extern "C" {
-
-alto_status alto_cpapr_pi(alto_handle h, int mode, int rank, const float *const *factors, float *pi, void *stream) {
-    alto_status st = check_phi_args(h, mode, rank, (const void *const *)factors, true);
-    if (st != ALTO_OK) return st;
-    if (!pi || ((uintptr_t)pi & 15)) return fail(ALTO_ERR_ARG, "pi must be a 16-byte aligned device pointer");
+alto_status run_pi(alto_tensor *h, int mode, int rank, const float *const *factors, float *pi, hipStream_t s) {
     if (h->info.nnz == 0) return ALTO_OK;
-    hipStream_t s = (hipStream_t)stream;
     h->stream = s;
     alto_mttkrp_plan p;
     memset(&p, 0, sizeof(p));
@@ -146,18 +148,25 @@ alto_status alto_cpapr_pi(alto_handle h, int mode, int rank, const float *const 
     return ALTO_OK;
 }
 
+}  // namespace alto
+
+using namespace alto;
+
+extern "C" {
+
+alto_status alto_cpapr_pi(alto_handle h, int mode, int rank, const float *const *factors, float *pi, void *stream) {
+    alto_status st = check_phi_args(h, mode, rank, (const void *const *)factors, true);
+    if (st != ALTO_OK) return st;
+    if (!pi || ((uintptr_t)pi & 15)) return fail(ALTO_ERR_ARG, "pi must be a 16-byte aligned device pointer");
+    return run_pi(h, mode, rank, factors, pi, (hipStream_t)stream);
+}
+
 alto_status alto_cpapr_prefer_pre(alto_handle h, int mode, int rank, int *pre) {
     ALTO_CHECK_HANDLE(h);
     if (!pre) return fail(ALTO_ERR_ARG, "pre is NULL");
     if (mode < 0 || mode >= h->info.nmodes) return fail(ALTO_ERR_ARG, "mode out of range");
     if (rank < 1) return fail(ALTO_ERR_ARG, "rank must be positive");
-    // low fiber reuse (the conflict-resolution rule's threshold) and factor
-    // matrices of the other modes well beyond the on-chip cache
-    const double reuse = (double)h->info.nnz / (double)h->info.dims[mode];
-    uint64_t fbytes = 0;
-    for (int m = 0; m < h->info.nmodes; m++)
-        if (m != mode) fbytes += h->info.dims[m] * (uint64_t)rank * 4;
-    *pre = (reuse <= 4.0 && fbytes > 2 * device_cache_bytes(h->device)) ? 1 : 0;
+    *pre = prefer_pre(h, mode, rank) ? 1 : 0;
     return ALTO_OK;
 }
 
