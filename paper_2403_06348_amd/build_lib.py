@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libalto_mi355x.so")
 SOURCES = ["plan.hip", "memory.hip", "build.hip", "mttkrp.hip", "mttkrp_f32_w1.hip", "mttkrp_f32_w2.hip",
-           "mttkrp_bf16_w1.hip", "mttkrp_bf16_w2.hip", "mttkrp_fast_f32.hip", "mttkrp_fast_bf16.hip", "als.hip", "fit.hip", "phi.hip", "cpapr.hip",
+           "mttkrp_bf16_w1.hip", "mttkrp_bf16_w2.hip", "mttkrp_fast_f32.hip", "mttkrp_fast_bf16.hip",
+           "mttkrp_fast64_f32.hip", "mttkrp_fast64_bf16.hip", "als.hip", "fit.hip", "phi.hip", "cpapr.hip",
            "batch.hip", "serve.hip"]
 ARCH = "gfx950"
 

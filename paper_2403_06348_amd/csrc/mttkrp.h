@@ -40,6 +40,7 @@ struct MttkrpArgs {
     uint32_t ld;      // row stride of factors and output (the full rank)
     uint32_t col0;    // first column of this rank tile
     uint64_t copy_stride;  // elements per copy
+    int lut;               // 1: 3 modes, one index word, <= 21 bits per mode (nibble-table decode)
     // CP-APR Phi forms: B (dims[mode] x ld FP32), Pi (nnz x ld FP32, ALTO
     // order; ALTO-PRE only), the divisor floor eps
     const float *phi_B;

@@ -22,6 +22,8 @@ const void *pick_lpn_bf16_w1(int lpn, int nmodes, bool batch);
 const void *pick_lpn_bf16_w2(int lpn, int nmodes, bool batch);
 const void *pick_fast_f32(int lpn, int tile_merge);
 const void *pick_fast_bf16(int lpn, int tile_merge);
+const void *pick_fast64_f32(int lpn, int tile_merge);
+const void *pick_fast64_bf16(int lpn, int tile_merge);
 
 const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch) {
     if (fdt == ALTO_BF16)
@@ -32,8 +34,10 @@ const void *pick_kernel(int lpn, int fdt, int words, int nmodes, bool batch) {
 // The specialised kernel serves 3-mode tensors with a one-word index whose
 // factor reads fit 32-bit offsets; everything else takes the general kernel.
 const void *pick_single(int lpn, int fdt, int words, const MttkrpArgs &a) {
-    if (words == 1 && a.nmodes == 3 && a.buf32)
+    if (words == 1 && a.nmodes == 3 && a.buf32) {
+        if (a.use64) return fdt == ALTO_BF16 ? pick_fast64_bf16(lpn, a.tile_merge) : pick_fast64_f32(lpn, a.tile_merge);
         return fdt == ALTO_BF16 ? pick_fast_bf16(lpn, a.tile_merge) : pick_fast_f32(lpn, a.tile_merge);
+    }
     return pick_kernel(lpn, fdt, words, a.nmodes, false);
 }
 
@@ -54,9 +58,10 @@ int device_cus(int dev) { return props(dev).cus; }
 size_t device_lds(int dev) { return props(dev).lds; }
 size_t device_cache_bytes(int dev) { return props(dev).cache; }
 
-// Static LDS of the MTTKRP kernels (extraction masks, counters) is below
-// this; plans budget it beside their tables and record staging.
-constexpr size_t kStaticLdsAllowance = 2048;
+// Static LDS of the MTTKRP kernels (extraction masks, the nibble decode
+// table, counters) is below this; plans budget it beside their tables and
+// record staging.
+constexpr size_t kStaticLdsAllowance = 4096;
 size_t static_lds_allowance() { return kStaticLdsAllowance; }
 
 // LDS words staged per nonzero: [value, destination, other coordinates]
@@ -436,6 +441,9 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
     while ((1 << l2) < p.table_slots) l2++;
     a->slots_log2 = l2;
     a->rec = record_words(h->info.nmodes, h->info.index_words);
+    a->lut = h->info.nmodes == 3 && h->info.index_words == 1;
+    for (int m = 0; m < h->info.nmodes; m++)
+        if (h->info.nbits[m] > 21) a->lut = 0;
     // whole-mode rows are FP64 when this rank tile fits so, else FP32
     a->tw = 2;
     if (a->tile_merge == 2 &&

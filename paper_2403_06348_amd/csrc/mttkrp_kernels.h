@@ -136,12 +136,15 @@ __device__ inline float4 widen(const uint2 &u) { return bf16x4_to_float4(u.x, u.
 __device__ inline uint32_t xcd_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 15u; }
 
 // Add 4 columns of partial sums (FP32 run sums or FP64 LDS rows) to the
-// output row, or to this XCD's copy of it, in FP32 or FP64.
-template <bool FAST = false, typename T>
+// output row, or to this XCD's copy of it, in FP32 or FP64.  FA: 0 reads the
+// accumulation type from the arguments; the specialised kernels fix it at
+// compile time (1: FP32, 2: FP64), which keeps the other form's code, and
+// the registers it holds, out of them.
+template <int FA = 0, typename T>
 __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, const T *acc) {
     uint64_t o = (uint64_t)row * a.ld + a.col0 + r0;
     if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
-    if (a.use64) {
+    if (FA == 2 || (FA == 0 && a.use64)) {
 #pragma unroll
         for (int j = 0; j < 4; j++)
             if (r0 + j < a.rank) unsafeAtomicAdd(a.out64 + o + j, (double)acc[j]);
@@ -158,11 +161,11 @@ __device__ inline void global_add(const MttkrpArgs &a, uint32_t row, int r0, con
 // instruction covers up to 16 columns (64 bytes) of a row: the L2 takes one
 // request per instruction and row segment, and 4-column pieces per lane
 // would cost four requests for the same 64 bytes.
-template <bool FAST = false, typename T>
+template <int FA = 0, typename T>
 __device__ inline void global_add1(const MttkrpArgs &a, uint32_t row, int c, T v) {
     uint64_t o = (uint64_t)row * a.ld + a.col0 + c;
     if (a.copies > 1) o += (uint64_t)(xcd_id() % (uint32_t)a.copies) * a.copy_stride;
-    if (a.use64) unsafeAtomicAdd(a.out64 + o, (double)v);
+    if (FA == 2 || (FA == 0 && a.use64)) unsafeAtomicAdd(a.out64 + o, (double)v);
     else unsafeAtomicAdd(a.out32 + o, (float)v);
 }
 
@@ -243,7 +246,7 @@ __device__ inline void lds_add4_f32(float *t, const float *v, int n) {
 // (ds_add_f64 against ds_add_f32), and the partial sums gain precision.  A
 // whole-mode table whose FP64 rows would not fit (a.tw == 1) holds FP32 rows,
 // twice the columns per pass, added by compare-and-swap.
-template <int TM, bool FAST>
+template <int TM, int FA>
 __device__ inline void flush_run(const MttkrpArgs &a, void *tval, uint32_t *thits, uint32_t dst, int q, int r0,
                                  const float *acc) {
     if (dst & kSlotBit) {
@@ -261,7 +264,7 @@ __device__ inline void flush_run(const MttkrpArgs &a, void *tval, uint32_t *thit
         if (q == 0 && tm == 1)
             __hip_atomic_fetch_add(thits + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
-        global_add<FAST>(a, dst, r0, acc);
+        global_add<FA>(a, dst, r0, acc);
     }
 }
 
@@ -300,7 +303,7 @@ __device__ inline Outbox outbox_of(uint32_t *obase, uint32_t *counts, int rank, 
 // consecutive columns; empties the outbox.  `n` is the entry count held in
 // a register (the same in every active lane); the LDS word mirrors it for
 // lanes that rejoin after leaving a loop early.
-template <bool FAST>
+template <int FA>
 __device__ inline void ob_drain(const Outbox &ob, const MttkrpArgs &a, uint32_t &cnt) {
     __builtin_amdgcn_wave_barrier();
     const uint32_t n = cnt;
@@ -313,7 +316,7 @@ __device__ inline void ob_drain(const Outbox &ob, const MttkrpArgs &a, uint32_t 
     for (int i = me; i < (int)n * rk; i += na) {
         int e, c;
         split_elem(i, rk, sh, &e, &c);
-        global_add1<FAST>(a, ob.rows[e], c, ob.vals[e * rk + c]);
+        global_add1<FA>(a, ob.rows[e], c, ob.vals[e * rk + c]);
     }
     __builtin_amdgcn_wave_barrier();
     cnt = 0u;
@@ -323,7 +326,7 @@ __device__ inline void ob_drain(const Outbox &ob, const MttkrpArgs &a, uint32_t 
 
 // Groups with `want` set (uniform inside a group) append row `row` (lane q
 // holds columns r0..r0+3 in acc) to the outbox.
-template <bool FAST>
+template <int FA>
 __device__ inline void ob_put(const Outbox &ob, const MttkrpArgs &a, bool want, uint32_t row, int q, int r0,
                               const float *acc, uint32_t &cnt) {
     const uint64_t bal = __ballot(want && q == 0);
@@ -336,7 +339,7 @@ __device__ inline void ob_put(const Outbox &ob, const MttkrpArgs &a, bool want, 
             if (q == 0) ob.rows[pos] = row;
             if (r0 < a.rank) *(float4 *)(ob.vals + (size_t)pos * a.rank + r0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
         } else {
-            global_add<FAST>(a, row, r0, acc);
+            global_add<FA>(a, row, r0, acc);
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -356,7 +359,7 @@ __device__ inline uint32_t rec_coord(const uint4 &h, const uint4 &h2, int k) {
 // hashed table (TM 1) every tile, except rows merged many times (high
 // reuse), which stay for the next tile.  Everything is flushed every
 // kKeepTiles tiles and at the end of the stretch.
-template <bool FAST>
+template <int FA>
 __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int TS, uint32_t *tkey, uint32_t *thits,
                                 void *tval, uint32_t &nkeep, uint64_t t, uint64_t t0, uint64_t t1) {
     const int tid = threadIdx.x;
@@ -374,10 +377,10 @@ __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int 
             split_elem(i, rk, sh, &row, &c);
             if (TW == 2) {
                 const double v = tv64[(size_t)row * TS + c];
-                if (v != 0.0) global_add1<FAST>(a, (uint32_t)row, c, v);
+                if (v != 0.0) global_add1<FA>(a, (uint32_t)row, c, v);
             } else {
                 const float v = tv32[(size_t)row * TS + c];
-                if (v != 0.f) global_add1<FAST>(a, (uint32_t)row, c, v);
+                if (v != 0.f) global_add1<FA>(a, (uint32_t)row, c, v);
             }
         }
         __syncthreads();
@@ -390,7 +393,7 @@ __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int 
             const uint32_t row = tkey[slot];
             if (row == kEmptyRow) continue;
             const double v = tv64[(size_t)slot * TS + c];
-            if (v != 0.0) global_add1<FAST>(a, row, c, v);
+            if (v != 0.0) global_add1<FA>(a, row, c, v);
         }
         __syncthreads();
     } else if (TM == 1) {
@@ -410,7 +413,7 @@ __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int 
             split_elem(i, rk, sh, &slot, &c);
             if (thits[slot] == kFlushMark) {
                 double *tv = tv64 + (size_t)slot * TS + c;
-                global_add1<FAST>(a, tkey[slot], c, *tv);
+                global_add1<FA>(a, tkey[slot], c, *tv);
                 *tv = 0.0;
             }
         }
@@ -678,6 +681,43 @@ __device__ inline void load_masks(const LinePlan &lp, int nmodes, uint64_t *lm) 
     __syncthreads();
 }
 
+// Coordinates of a 3-mode, one-word index whose modes have at most 21 bits
+// each, from a table of 16 nibble positions x 16 values in LDS: entry (c, v)
+// holds the bits of nibble c = v deposited into three 21-bit fields (mode m
+// at bit 21 m).  One LDS read and an OR per nibble replace
+// the three mask compressions (each six 64-bit steps with LDS masks).
+constexpr int kLutNibbles = 16;
+
+__device__ inline void build_nibble_lut(const uint64_t *lm, uint64_t *lut) {
+    for (int t = threadIdx.x; t < kLutNibbles * 16; t += blockDim.x) {
+        const int c = t >> 4, v = t & 15;
+        uint64_t e = 0;
+        for (int b = 0; b < 4; b++) {
+            if (!((v >> b) & 1)) continue;
+            const int p = 4 * c + b;
+            for (int m = 0; m < 3; m++) {
+                const uint64_t mask = lm[m * kMaskStride];  // word-0 mask of mode m
+                if ((mask >> p) & 1) e |= uint64_t(1) << (21 * m + __popcll(mask & ((uint64_t(1) << p) - 1)));
+            }
+        }
+        lut[t] = e;
+    }
+    __syncthreads();
+}
+
+// Used by the specialised kernel at up to 4 lanes per nonzero (rank <= 16):
+// there it cut the launch by about 3%; at 16 lanes (rank 64) the extra
+// registers it takes (68 -> 107 VGPRs) cost more than it saved.
+template <bool FAST, int WORDS, int LPN>
+constexpr bool kUseLut = FAST && WORDS == 1 && LPN <= 4;
+
+__device__ inline uint64_t lut_decode(const uint64_t *lut, uint64_t x) {
+    uint64_t acc = 0;
+#pragma unroll
+    for (int c = 0; c < kLutNibbles; c++) acc |= lut[c * 16 + (int)((x >> (4 * c)) & 15u)];
+    return acc;
+}
+
 // Coordinate of mode m from an index (lo, hi) with the masks in LDS.
 template <int WORDS>
 __device__ inline uint32_t extract_lds(const uint64_t *lm, int m, uint64_t lo, uint64_t hi) {
@@ -801,8 +841,8 @@ __device__ void hot_select(const MttkrpArgs &a, const uint64_t *lmask, uint64_t 
 // previous batch is already in registers when the next batch overwrites it
 // (a wave's LDS operations execute in order).  The two register sets of a
 // step (X and Y) alternate by hand, so nothing is copied.  FAST: exactly 3
-// modes, one-word index, 32-bit buffer gathers and FP32 atomics into the
-// output (the specialised kernel).
+// modes, one-word index and 32-bit buffer gathers (the specialised kernel);
+// FA: the accumulation type, fixed at compile time there (see global_add).
 //
 // OP selects what is accumulated per nonzero x (coordinates i, value v):
 //   kOpMttkrp: v * krp, krp = Hadamard product of the other factors' rows;
@@ -818,9 +858,10 @@ __device__ void hot_select(const MttkrpArgs &a, const uint64_t *lmask, uint64_t 
 // nonzero's position in the first coordinate word.
 constexpr int kOpMttkrp = 0, kOpPhi = 1, kOpPhiPre = 2;
 
-template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST, int OP = kOpMttkrp>
+template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST, int OP = kOpMttkrp, int FA = 0>
 __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep,
-                                           const uint64_t *lmask, uint64_t t0, uint64_t t1) {
+                                           const uint64_t *lmask, uint64_t t0, uint64_t t1,
+                                           const uint64_t *lut = nullptr) {
     static_assert(MAXO == 2 || MAXO == 4, "pipelined stretch: up to 5 modes");
     static_assert(OP == kOpMttkrp || (MAXO == 4 && !FAST), "Phi forms use 8-word records");
     const int TM = TMC >= 0 ? TMC : a.tile_merge;
@@ -911,8 +952,15 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
             r[1] = kEmptyRow;
             if (x < gb) {
                 uint32_t c[MAXO + 1];
+                if (kUseLut<FAST, WORDS, LPN> && a.lut) {
+                    const uint64_t e = lut_decode(lut, lo);
+                    c[0] = (uint32_t)(e & 0x1FFFFFu);
+                    c[1] = (uint32_t)((e >> 21) & 0x1FFFFFu);
+                    c[2] = (uint32_t)(e >> 42);
+                } else {
 #pragma unroll
-                for (int m = 0; m <= MAXO; m++) c[m] = m < nmodes ? extract_lds<WORDS>(lmask, m, lo, hi) : 0u;
+                    for (int m = 0; m <= MAXO; m++) c[m] = m < nmodes ? extract_lds<WORDS>(lmask, m, lo, hi) : 0u;
+                }
                 uint32_t row = c[0];
 #pragma unroll
                 for (int m = 1; m <= MAXO; m++)
@@ -1013,8 +1061,8 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
                 }
                 const bool same = live && dv[s] == cur;
                 const bool fl = live && !same && cur != kEmptyRow;
-                ob_put<FAST>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc, obn);
-                if (fl && (cur & kSlotBit)) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
+                ob_put<FA>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc, obn);
+                if (fl && (cur & kSlotBit)) flush_run<TMC, FA>(a, tval, thits, cur, q, r0, acc);
                 if (same) {
 #pragma unroll
                     for (int j = 0; j < 4; j++) acc[j] += p[j];
@@ -1023,7 +1071,7 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
 #pragma unroll
                     for (int j = 0; j < 4; j++) acc[j] = p[j];
                 }
-                if (obn > (uint32_t)(ob.cap - kGroupsPerWave)) ob_drain<FAST>(ob, a, obn);
+                if (obn > (uint32_t)(ob.cap - kGroupsPerWave)) ob_drain<FA>(ob, a, obn);
             }
         };
 
@@ -1045,12 +1093,12 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
             __builtin_amdgcn_wave_barrier();
             obn = *(volatile uint32_t *)ob.count;
             const bool fl = cur != kEmptyRow;
-            ob_put<FAST>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc, obn);
-            if (fl && (cur & kSlotBit)) flush_run<TMC, FAST>(a, tval, thits, cur, q, r0, acc);
+            ob_put<FA>(ob, a, fl && !(cur & kSlotBit), cur, q, r0, acc, obn);
+            if (fl && (cur & kSlotBit)) flush_run<TMC, FA>(a, tval, thits, cur, q, r0, acc);
         }
-        ob_drain<FAST>(ob, a, obn);
+        ob_drain<FA>(ob, a, obn);
         __builtin_amdgcn_wave_barrier();
-        tile_end<FAST>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
+        tile_end<FA>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
     }
 }
 
@@ -1066,18 +1114,21 @@ __device__ inline void stretch_of(uint64_t total, int xcd_map, uint64_t *g0, uin
 
 // Kernel variants: MAXO = most other modes handled with fully unrolled
 // gathers (2: up to 3-mode tensors, 4: up to 5 modes); 7: any order, rolled.
-template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST>
+template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST, bool F64 = false>
 __global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ uint32_t nkeep;
     __shared__ uint64_t lmask[(FAST || MAXO <= 4) ? kMaskWords : 1];
+    __shared__ uint64_t lut[kUseLut<FAST, WORDS, LPN> ? kLutNibbles * 16 : 1];
     uint64_t t0, t1;
     stretch_of(a.ntiles, a.xcd_map, &t0, &t1);
     // the pipelined loop (with the per-wave outboxes) for up to 5 modes; the
     // plain loop for 6-8 modes
     if constexpr (FAST || MAXO <= 4) {
         load_masks(a.lp, a.nmodes, lmask);
-        mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, TMC, FAST>(a, smem, nkeep, lmask, t0, t1);
+        if (kUseLut<FAST, WORDS, LPN> && a.lut) build_nibble_lut(lmask, lut);
+        mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, TMC, FAST, kOpMttkrp, FAST ? (F64 ? 2 : 1) : 0>(a, smem, nkeep, lmask,
+                                                                                              t0, t1, lut);
     } else {
         mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC>(a, smem, nkeep, t0, t1);
     }
@@ -1195,23 +1246,23 @@ const void *kernel_ptr(int nmodes, bool batch) {
     return batch ? (const void *)k_mttkrp_batch<LPN, FT, WORDS, 7> : (const void *)k_mttkrp<LPN, FT, WORDS, 7, -1, false>;
 }
 
-template <int LPN, typename FT>
+template <int LPN, typename FT, bool F64>
 const void *fast_ptr(int tile_merge) {
-    return tile_merge == 1   ? (const void *)k_mttkrp<LPN, FT, 1, 2, 1, true>
-           : tile_merge == 2 ? (const void *)k_mttkrp<LPN, FT, 1, 2, 2, true>
-           : tile_merge == 3 ? (const void *)k_mttkrp<LPN, FT, 1, 2, 3, true>
-                             : (const void *)k_mttkrp<LPN, FT, 1, 2, 0, true>;
+    return tile_merge == 1   ? (const void *)k_mttkrp<LPN, FT, 1, 2, 1, true, F64>
+           : tile_merge == 2 ? (const void *)k_mttkrp<LPN, FT, 1, 2, 2, true, F64>
+           : tile_merge == 3 ? (const void *)k_mttkrp<LPN, FT, 1, 2, 3, true, F64>
+                             : (const void *)k_mttkrp<LPN, FT, 1, 2, 0, true, F64>;
 }
 
-template <typename FT>
+template <typename FT, bool F64>
 const void *pick_fast(int lpn, int tile_merge) {
     switch (lpn) {
-        case 1: return fast_ptr<1, FT>(tile_merge);
-        case 2: return fast_ptr<2, FT>(tile_merge);
-        case 4: return fast_ptr<4, FT>(tile_merge);
-        case 8: return fast_ptr<8, FT>(tile_merge);
-        case 16: return fast_ptr<16, FT>(tile_merge);
-        default: return fast_ptr<32, FT>(tile_merge);
+        case 1: return fast_ptr<1, FT, F64>(tile_merge);
+        case 2: return fast_ptr<2, FT, F64>(tile_merge);
+        case 4: return fast_ptr<4, FT, F64>(tile_merge);
+        case 8: return fast_ptr<8, FT, F64>(tile_merge);
+        case 16: return fast_ptr<16, FT, F64>(tile_merge);
+        default: return fast_ptr<32, FT, F64>(tile_merge);
     }
 }
 
