@@ -705,9 +705,11 @@ __device__ inline void build_nibble_lut(const uint64_t *lm, uint64_t *lut) {
     __syncthreads();
 }
 
-// Used by the specialised kernel at up to 4 lanes per nonzero (rank <= 16):
-// there it cut the launch by about 3%; at 16 lanes (rank 64) the extra
-// registers it takes (68 -> 107 VGPRs) cost more than it saved.
+// Used by the specialised kernel at up to 4 lanes per nonzero (rank <= 16),
+// where decoding is a large share of each lane's work: c2 (R=16) MTTKRP
+// calls 2.02 / 1.98 / 2.12 -> 1.92 / 1.94 / 2.07 ms.  At 16 lanes (R=64)
+// one decode serves 16 lanes' gathers and products, and the table's LDS
+// reads measured slower (8.4 -> 8.6 ms and 8.9 -> 9.2 ms on modes 1 and 2).
 template <bool FAST, int WORDS, int LPN>
 constexpr bool kUseLut = FAST && WORDS == 1 && LPN <= 4;
 
