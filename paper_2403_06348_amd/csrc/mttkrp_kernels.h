@@ -707,7 +707,7 @@ __device__ inline void build_nibble_lut(const uint64_t *lm, uint64_t *lut) {
 
 // Used by the specialised kernel at up to 4 lanes per nonzero (rank <= 16),
 // where decoding is a large share of each lane's work: c2 (R=16) MTTKRP
-// calls 2.02 / 1.98 / 2.12 -> 1.92 / 1.94 / 2.07 ms.  At 16 lanes (R=64)
+// calls 2.08 / 2.06 / 2.18 -> 2.02 / 1.98 / 2.12 ms.  At 16 lanes (R=64)
 // one decode serves 16 lanes' gathers and products, and the table's LDS
 // reads measured slower (8.4 -> 8.6 ms and 8.9 -> 9.2 ms on modes 1 and 2).
 template <bool FAST, int WORDS, int LPN>
