@@ -92,7 +92,14 @@ typedef enum {
  * ALTO_ACC_F32: directly in the FP32 output with FP32 atomics.
  * ALTO_ACC_XCD_F32 / ALTO_ACC_XCD_F64: in one private FP32 / FP64 copy of the
  *   output per XCD (the chiplet a workgroup runs on), summed in FP64 and
- *   rounded once to FP32 at the end; atomics of different XCDs never meet. */
+ *   rounded once to FP32 at the end; atomics of different XCDs never meet.
+ * ALTO_ACC_DEFAULT (0): the library's accuracy policy.  FP32 atomics only
+ *   where an output entry can take at most 256 additions (each can round
+ *   away up to half a unit in the last place of the entry's running sum);
+ *   else FP64: per-XCD copies for short modes with at least 512 nonzeros per
+ *   row whose 8 copies take at most 1 GiB, otherwise one buffer (the
+ *   autotuner times both).  Every entry then stays within 1e-5 of the sum of
+ *   its terms' magnitudes. */
 typedef enum {
     ALTO_ACC_DEFAULT = 0,
     ALTO_ACC_F64 = 1,
