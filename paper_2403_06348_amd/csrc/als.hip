@@ -528,15 +528,22 @@ __global__ __launch_bounds__(kThreads) void k_als_finalize(double *__restrict__ 
     als_finalize(Gn, R, lam_ws, lam_out);
 }
 
+// A(:, c) /= lambda_c over elements start, start + stride, ...; the column
+// advances by stride mod R per step (no division per element).
 __device__ inline void als_normalize(float *__restrict__ A, uint64_t I, int R, const double *__restrict__ lam,
                                      uint16_t *__restrict__ shadow, uint64_t start, uint64_t stride) {
     const uint64_t n = I * R;
+    if (start >= n) return;
+    const uint32_t step = (uint32_t)(stride % (uint64_t)R);
+    uint32_t c = (uint32_t)(start % (uint64_t)R);
     for (uint64_t t = start; t < n; t += stride) {
-        const double l = lam[t % R];
+        const double l = lam[c];
         float v = A[t];
         if (l > 0.0) v = (float)((double)v / l);
         A[t] = v;
         if (shadow) shadow[t] = f32_to_bf16_rne(v);
+        c += step;
+        if (c >= (uint32_t)R) c -= (uint32_t)R;
     }
 }
 
@@ -580,10 +587,15 @@ __global__ __launch_bounds__(kThreads) void k_als_finalize_b(const SweepJob *__r
     als_finalize(j.G, j.R, j.lam_ws, j.lam_out);
 }
 
-__global__ void k_als_normalize_b(const SweepJob *__restrict__ jobs) {
-    const SweepJob &j = jobs[blockIdx.x];
-    als_normalize(j.A, j.I, j.R, j.lam_ws, j.shadow, (uint64_t)blockIdx.y * blockDim.x + threadIdx.x,
-                  (uint64_t)gridDim.y * blockDim.x);
+// Every workgroup takes part in every job (grid-stride within each job), so
+// a job's share of the grid does not depend on its position or size.
+__global__ void k_als_normalize_b(const SweepJob *__restrict__ jobs, int nj) {
+    const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (int k = 0; k < nj; k++) {
+        const SweepJob &j = jobs[k];
+        als_normalize(j.A, j.I, j.R, j.lam_ws, j.shadow, start, stride);
+    }
 }
 
 __global__ void k_to_bf16(const float *__restrict__ A, uint64_t n, uint16_t *__restrict__ out) {
@@ -880,10 +892,11 @@ alto_status batched_sweep_setup(int count, const alto_handle *hs, const int *ran
         }
     }
     bs->sec[maxN] = bs->table.size();
-    // normalization workgroups per job: enough for the largest factor
+    // normalization grid (every workgroup takes part in every job): enough
+    // workgroups for the largest factor
     uint64_t maxIR = 1;
     for (const SweepJob &jb : bs->table) maxIR = std::max<uint64_t>(maxIR, jb.I * (uint64_t)jb.R);
-    bs->nblk = (unsigned)std::min<uint64_t>(512, (maxIR + 2047) / 2048);
+    bs->nblk = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(4096, (maxIR + 2047) / 2048));
     bs->rblocks = gram_reduce_blocks(bs->maxR);
     bs->fptr.assign((size_t)count * ALTO_MAX_MODES, nullptr);
     for (int j = 0; j < count; j++)
@@ -971,7 +984,7 @@ alto_status batched_sweep_launch(const BatchedSweep &bs, const SweepJob *dtab, c
         }
         hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, bs.rblocks), dim3(kThreads), 0, s, dtab + bs.sec[n]);
         hipLaunchKernelGGL(k_als_finalize_b, dim3(nj), dim3(kThreads), 0, s, dtab + bs.sec[n]);
-        hipLaunchKernelGGL(k_als_normalize_b, dim3(nj, bs.nblk), dim3(256), 0, s, dtab + bs.sec[n]);
+        hipLaunchKernelGGL(k_als_normalize_b, dim3(bs.nblk), dim3(256), 0, s, dtab + bs.sec[n], (int)nj);
         ALTO_HIP(hipGetLastError());
     }
     return ALTO_OK;

@@ -31,10 +31,15 @@ __global__ __launch_bounds__(kAprThreads) void k_apr_prep(const float *__restric
                                                           const float *__restrict__ phi_prev, double kappa,
                                                           double kappa_tol, float *__restrict__ B) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t step = (uint32_t)(stride % (uint64_t)R);
+    uint32_t c = (uint32_t)(start % (uint64_t)R);  // column of t, advanced without a division per element
+    for (uint64_t t = start; t < n; t += stride) {
         const double a = A[t];
         const double s = (phi_prev && a < kappa_tol && phi_prev[t] > 1.f) ? kappa : 0.0;
-        B[t] = (float)((a + s) * lam[t % (uint64_t)R]);
+        B[t] = (float)((a + s) * lam[c]);
+        c += step;
+        if (c >= (uint32_t)R) c -= (uint32_t)R;
     }
 }
 
@@ -107,9 +112,14 @@ __global__ __launch_bounds__(kAprThreads) void k_apr_colsum_final(const double *
 __global__ __launch_bounds__(kAprThreads) void k_apr_normalize(const float *__restrict__ B, uint64_t n, int R,
                                                                const double *__restrict__ lam, float *__restrict__ A) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
-        const double l = lam[t % (uint64_t)R];
+    const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t step = (uint32_t)(stride % (uint64_t)R);
+    uint32_t c = (uint32_t)(start % (uint64_t)R);
+    for (uint64_t t = start; t < n; t += stride) {
+        const double l = lam[c];
         A[t] = l > 0.0 ? (float)((double)B[t] / l) : 0.f;
+        c += step;
+        if (c >= (uint32_t)R) c -= (uint32_t)R;
     }
 }
 
