@@ -53,10 +53,13 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 // the chunk's rows in FP64.  At the end the row groups' tiles are added in
 // a fixed order and the block writes its partial R x R Gram.
 // RB: rank bucket (8, 16, 32, 64), R <= RB, R a multiple of 4.
+// blk / nblk: this workgroup's chunk of the rows and the chunk count (the
+// partial Gram it writes).  shadow (not APPLY): also store the BF16 copy of
+// the staged rows.
 template <int RB, bool APPLY>
-__global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict__ src, const double *__restrict__ W,
-                                                        float *__restrict__ A, uint64_t I, int R,
-                                                        double *__restrict__ partials) {
+__device__ inline void gram_rows_body(const float *__restrict__ src, const double *__restrict__ W,
+                                      float *__restrict__ A, uint64_t I, int R, double *__restrict__ partials,
+                                      uint16_t *__restrict__ shadow, unsigned blk, unsigned nblk) {
     constexpr int STR = RB + 4;             // LDS row stride (floats), 16-byte aligned
     constexpr int TPR = RB / 4;             // 4 x 4 tiles per Gram row
     constexpr int TB = TPR * TPR;           // tiles of the Gram
@@ -75,8 +78,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict_
     for (int x = 0; x < 4; x++)
 #pragma unroll
         for (int y = 0; y < 4; y++) acc[x][y] = 0.0;
-    const uint64_t per = (I + gridDim.x - 1) / gridDim.x;
-    const uint64_t a = (uint64_t)blockIdx.x * per;
+    const uint64_t per = (I + nblk - 1) / nblk;
+    const uint64_t a = (uint64_t)blk * per;
     const uint64_t b = a + per < I ? a + per : I;
     const int q4 = R / 4;
     for (uint64_t c = a; c < b; c += kThreads) {
@@ -85,7 +88,13 @@ __global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict_
         const float4 *s4 = (const float4 *)(src + c * R);
         for (int v = tid; v < rows * q4; v += kThreads) {
             const int row = v / q4, q = v - row * q4;
-            *(float4 *)(sa + row * STR + 4 * q) = s4[v];
+            const float4 f = s4[v];
+            *(float4 *)(sa + row * STR + 4 * q) = f;
+            if (!APPLY && shadow) {
+                const uint32_t lo = (uint32_t)f32_to_bf16_rne(f.x) | ((uint32_t)f32_to_bf16_rne(f.y) << 16);
+                const uint32_t hi = (uint32_t)f32_to_bf16_rne(f.z) | ((uint32_t)f32_to_bf16_rne(f.w) << 16);
+                ((uint2 *)(shadow + c * R))[v] = make_uint2(lo, hi);
+            }
         }
         __syncthreads();
         if (APPLY && RB >= 32) {
@@ -208,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict_
 #pragma unroll
         for (int w = 0; w < 4; w++) red[((size_t)g * TB + t) * 16 + u * 4 + w] = acc[u][w];
     __syncthreads();
-    double *o = partials + (uint64_t)blockIdx.x * R * R;
+    double *o = partials + (uint64_t)blk * R * R;
     for (int e = tid; e < R * R; e += kThreads) {
         const int r = e / R, c2 = e % R;
         const int tt = (r / 4) * TPR + c2 / 4, pos = (r % 4) * 4 + c2 % 4;
@@ -216,6 +225,13 @@ __global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict_
         for (int k = 0; k < G; k++) sum += red[((size_t)k * TB + tt) * 16 + pos];
         o[e] = sum;
     }
+}
+
+template <int RB, bool APPLY>
+__global__ __launch_bounds__(kThreads) void k_gram_rows(const float *__restrict__ src, const double *__restrict__ W,
+                                                        float *__restrict__ A, uint64_t I, int R,
+                                                        double *__restrict__ partials) {
+    gram_rows_body<RB, APPLY>(src, W, A, I, R, partials, nullptr, blockIdx.x, gridDim.x);
 }
 
 // G = sum of the np partial R x R blocks.  Block b owns entries
@@ -560,20 +576,40 @@ struct SweepJob {
     const double *grams;     // N x R x R Grams
     double *W;               // R x R solve operator
     uint32_t *flags;         // pseudo-inverse fallback flags
-    const double *partials;  // P partial R x R Grams
+    double *partials;        // P partial R x R Grams
     double *G;               // Gram the partials are summed into
     double *lam_ws;          // lambda of the mode (workspace)
     double *lam_out;         // caller's lambda (last mode) or null
     float *A;                // factor to normalize
     uint16_t *shadow;        // its BF16 shadow or null
+    const float *M;          // the mode's MTTKRP result
     uint64_t I;
     int N, n, R, P;
+    uint32_t blk0;           // first workgroup of the job in its Gram launch
 };
 
 __global__ __launch_bounds__(kThreads) void k_als_prepare_b(const SweepJob *__restrict__ jobs) {
     extern __shared__ double sm[];
     const SweepJob &j = jobs[blockIdx.x];
     als_prepare(j.grams, j.N, j.n, j.R, j.R, j.W, j.flags, sm);
+}
+
+// Row-chunk Grams of many jobs of one rank bucket in one launch: workgroup
+// w works on job k where blk0_k <= w < blk0_k + P_k (blk0 ascending).  Not
+// APPLY: Gram of the factor A (and its BF16 shadow); APPLY: A = M W and the
+// Gram of the new A.
+template <int RB, bool APPLY>
+__global__ __launch_bounds__(kThreads) void k_gram_rows_b(const SweepJob *__restrict__ jobs, int nj) {
+    const unsigned w = blockIdx.x;
+    int lo = 0, hi = nj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].blk0 <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const SweepJob &j = jobs[lo];
+    gram_rows_body<RB, APPLY>(APPLY ? j.M : j.A, j.W, j.A, j.I, j.R, j.partials, APPLY ? nullptr : j.shadow,
+                              w - j.blk0, (unsigned)j.P);
 }
 
 __global__ __launch_bounds__(kThreads) void k_gram_reduce_b(const SweepJob *__restrict__ jobs) {
@@ -614,6 +650,16 @@ void launch_gram_rows(int R, unsigned P, hipStream_t s, const float *src, const 
         case 16: hipLaunchKernelGGL((k_gram_rows<16, APPLY>), dim3(P), dim3(kThreads), 0, s, src, W, A, I, R, partials); break;
         case 32: hipLaunchKernelGGL((k_gram_rows<32, APPLY>), dim3(P), dim3(kThreads), 0, s, src, W, A, I, R, partials); break;
         default: hipLaunchKernelGGL((k_gram_rows<64, APPLY>), dim3(P), dim3(kThreads), 0, s, src, W, A, I, R, partials); break;
+    }
+}
+
+template <bool APPLY>
+void launch_gram_rows_b(int rb, unsigned blocks, hipStream_t s, const SweepJob *jobs, int nj) {
+    switch (rb) {
+        case 8: hipLaunchKernelGGL((k_gram_rows_b<8, APPLY>), dim3(blocks), dim3(kThreads), 0, s, jobs, nj); break;
+        case 16: hipLaunchKernelGGL((k_gram_rows_b<16, APPLY>), dim3(blocks), dim3(kThreads), 0, s, jobs, nj); break;
+        case 32: hipLaunchKernelGGL((k_gram_rows_b<32, APPLY>), dim3(blocks), dim3(kThreads), 0, s, jobs, nj); break;
+        default: hipLaunchKernelGGL((k_gram_rows_b<64, APPLY>), dim3(blocks), dim3(kThreads), 0, s, jobs, nj); break;
     }
 }
 
@@ -792,6 +838,14 @@ struct BatchedSweep {
     std::vector<const void *> fptr;    // count x ALTO_MAX_MODES gathered factors (BF16 shadows)
     std::vector<SweepJob> table;
     std::vector<size_t> sec;
+    // per mode: the Gram launches, one per rank bucket (table range, bucket,
+    // workgroups)
+    struct GramRange {
+        size_t b0;
+        int nj, rb;
+        unsigned blocks;
+    };
+    std::vector<std::vector<GramRange>> granges;
     unsigned nblk = 1, rblocks = 1;
 };
 
@@ -883,15 +937,35 @@ alto_status batched_sweep_setup(int count, const alto_handle *hs, const int *ran
             jb.lam_out = m == h->info.nmodes - 1 ? lambdas[j] : nullptr;
             jb.A = factors[j][m];
             jb.shadow = fdts[j] == ALTO_BF16 ? h->ws_bf16[m] : nullptr;
+            jb.M = h->ws_m;
             jb.I = h->info.dims[m];
             jb.N = h->info.nmodes;
             jb.n = m;
             jb.R = R;
             jb.P = (int)partial_blocks(jb.I);
+            jb.blk0 = 0;
             bs->table.push_back(jb);
         }
+        // the mode's jobs ordered by rank bucket: one Gram launch per bucket
+        auto first = bs->table.begin() + bs->sec[m];
+        std::stable_sort(first, bs->table.end(), [](const SweepJob &x, const SweepJob &y) {
+            return rank_bucket(x.R) < rank_bucket(y.R);
+        });
     }
     bs->sec[maxN] = bs->table.size();
+    bs->granges.assign(maxN, {});
+    for (int m = 0; m < maxN; m++) {
+        for (size_t k = bs->sec[m]; k < bs->sec[m + 1];) {
+            const int rb = rank_bucket(bs->table[k].R);
+            BatchedSweep::GramRange g{k, 0, rb, 0};
+            for (; k < bs->sec[m + 1] && rank_bucket(bs->table[k].R) == rb; k++) {
+                bs->table[k].blk0 = g.blocks;
+                g.blocks += (unsigned)bs->table[k].P;
+                g.nj++;
+            }
+            bs->granges[m].push_back(g);
+        }
+    }
     // normalization grid (every workgroup takes part in every job): enough
     // workgroups for the largest factor
     uint64_t maxIR = 1;
@@ -913,9 +987,8 @@ alto_status batched_sweep_launch(const BatchedSweep &bs, const SweepJob *dtab, c
     // Grams of every factor: the partials of mode m for every job, then one
     // reduction launch (each job's partial buffer is reused mode by mode)
     for (int m = 0; m < bs.maxN; m++) {
-        for (int j = 0; j < count; j++)
-            if (m < bs.hs[j]->info.nmodes)
-                gram_partials(bs.hs[j], m, bs.ranks[j], bs.fdts[j], &bs.facs[(size_t)j * ALTO_MAX_MODES], s);
+        for (const BatchedSweep::GramRange &g : bs.granges[m])
+            launch_gram_rows_b<false>(g.rb, g.blocks, s, dtab + g.b0, g.nj);
         const unsigned nj = (unsigned)(bs.sec[m + 1] - bs.sec[m]);
         hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, bs.rblocks), dim3(kThreads), 0, s, dtab + bs.sec[m]);
     }
@@ -970,18 +1043,10 @@ alto_status batched_sweep_launch(const BatchedSweep &bs, const SweepJob *dtab, c
                                           bout.data(), s);
             if (st != ALTO_OK) return st;
         }
-        // A = M W with the partial Grams of A, per job (the real work), then
-        // the Gram sums, lambda and normalization in one launch each
-        for (int j = 0; j < count; j++) {
-            if (n >= bs.hs[j]->info.nmodes) continue;
-            alto_tensor *h = bs.hs[j];
-            const int R = bs.ranks[j];
-            const size_t rr = (size_t)R * R;
-            double *W = (double *)h->ws_sweep + h->info.nmodes * rr;
-            const uint64_t I = h->info.dims[n];
-            launch_gram_rows<true>(R, partial_blocks(I), s, h->ws_m, W, bs.facs[(size_t)j * ALTO_MAX_MODES + n], I,
-                                   W + rr);
-        }
+        // A = M W with the partial Grams of A (one launch per rank bucket),
+        // then the Gram sums, lambda and normalization in one launch each
+        for (const BatchedSweep::GramRange &g : bs.granges[n])
+            launch_gram_rows_b<true>(g.rb, g.blocks, s, dtab + g.b0, g.nj);
         hipLaunchKernelGGL(k_gram_reduce_b, dim3(nj, bs.rblocks), dim3(kThreads), 0, s, dtab + bs.sec[n]);
         hipLaunchKernelGGL(k_als_finalize_b, dim3(nj), dim3(kThreads), 0, s, dtab + bs.sec[n]);
         hipLaunchKernelGGL(k_als_normalize_b, dim3(bs.nblk), dim3(256), 0, s, dtab + bs.sec[n], (int)nj);

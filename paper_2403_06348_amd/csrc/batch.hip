@@ -45,7 +45,8 @@ alto_status plan_group(const Group &g, const alto_handle *hs, const int *modes, 
         // FP32 atomics into the output: a row takes at most one addition per
         // tile, so long tensors get longer tiles (see accuracy_policy)
         p.tile_nnz = (int)std::max<uint64_t>((uint64_t)tile, (h->info.nnz + kBatchF32MaxTiles - 1) / kBatchF32MaxTiles);
-        p.table_slots = std::max(16, p.table_slots * slots_factor / 2);
+        // table rows: slots_factor quarters of the single-tensor default
+        p.table_slots = std::max(16, p.table_slots * slots_factor / 4);
         // one LDS size serves the whole launch: keep every table within
         // 96 KiB of FP64 rows, keys and hit counts
         while (p.table_slots > 16 && (size_t)p.table_slots * (2 * (ranks[j] + 1) + 2) * 4 > 96 * 1024)
@@ -158,9 +159,9 @@ alto_status group_items(int count, const alto_handle *hs, const int *modes, cons
             ALTO_HIP(hipEventCreate(&e0));
             ALTO_HIP(hipEventCreate(&e1));
             float best = 1e30f;
-            std::pair<int, int> bestp = {4096, 2};
-            for (int tile : {1024, 4096, 16384}) {
-                for (int f : {2, 4}) {
+            std::pair<int, int> bestp = {4096, 4};
+            for (int tile : {1024, 4096}) {
+                for (int f : {1, 2, 4}) {
                     alto_status st = launch_group(g, hs, modes, ranks, factors, outs, tile, f, s, dev);
                     if (st != ALTO_OK) return st;
                     ALTO_HIP(hipEventRecord(e0, s));

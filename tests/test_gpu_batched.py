@@ -111,6 +111,33 @@ def test_batched_sweep_matches_separate_sweeps():
         T.free()
 
 
+def test_batched_sweep_mixed_factor_types_match_oracle():
+    """A batched sweep whose items alternate BF16-stored and FP32 factors
+    (the BF16 shadows are written by the batched Gram launches and refreshed
+    by the normalization): every mode of every item against the oracle's
+    update, from the BF16-rounded factors for the BF16 items."""
+    specs = job_specs()[:6]
+    jobs, items = [], []
+    for k, (dims, nnz, ex, R, seed) in enumerate(specs):
+        R = min(R, 32)
+        X = zipf_tensor(dims, nnz, ex, seed=seed)
+        T = alto.AltoTensor(X.dims, torch.from_numpy(X.coords).cuda(), torch.from_numpy(vals32(X)).cuda())
+        f0 = [torch.from_numpy(f).cuda() for f in make_factors(X.dims, R, seed=seed + 2)]
+        fdt = alto.BF16 if k % 2 == 0 else alto.F32
+        jobs.append((X, T, f0, fdt))
+        items.append((T, [f.clone() for f in f0], torch.empty(R, dtype=torch.float64, device="cuda"), fdt))
+    say(f"[batched] mixed BF16/FP32 sweep of {len(items)} tensors")
+    alto.sweep_batched(items)
+    torch.cuda.synchronize()
+    for k, (it, (X, _, f0, fdt)) in enumerate(zip(items, jobs)):
+        check_sweep(X.dims, X.coords, vals32(X), [f.cpu().numpy() for f in f0],
+                    [f.cpu().numpy() for f in it[1]], it[2].cpu().numpy(),
+                    what=f"mixed item {k} ({'bf16' if fdt == alto.BF16 else 'f32'})",
+                    quantize=(fdt == alto.BF16))
+    for _, T, _, _ in jobs:
+        T.free()
+
+
 def test_prepared_batch_graph_replays_match_oracle():
     """A prepared batched sweep (alto_sweep_batch_*) captured in one HIP
     graph.  Its eager run and every replay -- with eager work and
