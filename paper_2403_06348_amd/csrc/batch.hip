@@ -2,6 +2,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <string>
@@ -21,15 +22,21 @@ struct Group {
     std::vector<int> items;
 };
 
+// Launch plan of a group: tile length, LDS table rows (quarters of the
+// single-tensor default), threads per workgroup.
+using BatchPlan = std::array<int, 3>;
+
 int maxo_of(int nmodes) { return nmodes <= 3 ? 2 : (nmodes <= 5 ? 4 : 7); }
 
 // Host side of one group's persistent launch: the per-job kernel arguments,
 // tile and output prefixes, LDS size and kernel.
 alto_status plan_group(const Group &g, const alto_handle *hs, const int *modes, const int *ranks,
-                       const void *const *const *factors, float *const *outs, int tile, int slots_factor,
+                       const void *const *const *factors, float *const *outs, const BatchPlan &bp,
                        hipStream_t s, int dev, GroupLaunch *gl) {
     const int nj = (int)g.items.size();
+    const int tile = bp[0], slots_factor = bp[1], threads = bp[2];
     gl->nj = nj;
+    gl->threads = threads;
     gl->jobs.assign(nj, MttkrpArgs{});
     gl->prefix.assign(nj + 1, 0);
     gl->oprefix.assign(nj + 1, 0);
@@ -56,7 +63,7 @@ alto_status plan_group(const Group &g, const alto_handle *hs, const int *modes, 
         const uint64_t tiles = h->info.nnz == 0 ? 0 : gl->jobs[k].ntiles;
         gl->prefix[k + 1] = gl->prefix[k] + tiles;
         gl->oprefix[k + 1] = gl->oprefix[k] + h->info.dims[modes[j]] * (uint64_t)ranks[j];
-        lds = std::max(lds, lds_bytes(gl->jobs[k], 256));
+        lds = std::max(lds, lds_bytes(gl->jobs[k], threads));
     }
     gl->lds = lds;
     gl->kern = pick_kernel(g.lpn, g.fdt, g.words, gl->jobs[0].nmodes, true);
@@ -64,7 +71,7 @@ alto_status plan_group(const Group &g, const alto_handle *hs, const int *modes, 
     alto_status lst = check_launch_lds(gl->kern, lds, dev);
     if (lst != ALTO_OK) return lst;
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gl->kern, 256, lds) != hipSuccess || occ < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gl->kern, threads, lds) != hipSuccess || occ < 1) {
         (void)hipGetLastError();
         occ = 1;
     }
@@ -90,10 +97,10 @@ std::mutex g_stage_mu;
 std::map<std::pair<int, hipStream_t>, Staging> g_stage;
 
 alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes, const int *ranks,
-                         const void *const *const *factors, float *const *outs, int tile, int slots_factor,
+                         const void *const *const *factors, float *const *outs, const BatchPlan &bp,
                          hipStream_t s, int dev) {
     GroupLaunch gl;
-    alto_status st0 = plan_group(g, hs, modes, ranks, factors, outs, tile, slots_factor, s, dev, &gl);
+    alto_status st0 = plan_group(g, hs, modes, ranks, factors, outs, bp, s, dev, &gl);
     if (st0 != ALTO_OK) return st0;
     const size_t need = gl.blob_bytes();
     Staging *st;
@@ -116,16 +123,16 @@ alto_status launch_group(const Group &g, const alto_handle *hs, const int *modes
     return launch_planned_group(gl, st->dev, s);
 }
 
-// Tuned (tile, table rows) per kernel-variant group and total-size class.
+// Tuned launch plan per kernel-variant group and item-size class.
 std::mutex g_btune_mu;
-std::map<std::array<int, 6>, std::pair<int, int>> g_btune;
+std::map<std::array<int, 6>, BatchPlan> g_btune;
 
 // Groups of the items by kernel variant, each with its tuned (tile, table
 // factor); the first sight of a group class times a few plans (launching
 // them, and waiting for them, on stream s).
 alto_status group_items(int count, const alto_handle *hs, const int *modes, const int *ranks, const int *fdts,
                         const void *const *const *factors, float *const *outs, hipStream_t s, int dev,
-                        std::vector<std::pair<Group, std::pair<int, int>>> *out) {
+                        std::vector<std::pair<Group, BatchPlan>> *out) {
     std::map<std::array<int, 4>, Group> groups;
     for (int j = 0; j < count; j++) {
         const std::array<int, 4> key = {lpn_for(ranks[j]), fdts[j], hs[j]->info.index_words,
@@ -147,25 +154,32 @@ alto_status group_items(int count, const alto_handle *hs, const int *modes, cons
         const double avg = nnz > 0 ? (double)nnz / g.items.size() : 1.0;
         const int ln = (int)std::floor(std::log2(avg) / 2.0);
         const std::array<int, 6> tkey = {g.lpn, g.fdt, g.words, g.maxo, ln, 0};
-        std::pair<int, int> tuned = {0, 0};
+        BatchPlan tuned = {0, 0, 0};
         {
             std::lock_guard<std::mutex> lk(g_btune_mu);
             auto it = g_btune.find(tkey);
             if (it != g_btune.end()) tuned = it->second;
         }
-        if (tuned.first == 0) {
-            // first sight of this group class: time a few (tile, table) plans
+        if (tuned[0] == 0) {
+            // first sight of this group class: time a few (tile, table, block) plans
             hipEvent_t e0, e1;
             ALTO_HIP(hipEventCreate(&e0));
             ALTO_HIP(hipEventCreate(&e1));
             float best = 1e30f;
-            std::pair<int, int> bestp = {4096, 4};
+            // candidates: the winners of a sweep over tile {1024, 4096} x
+            // table {1/4, 1/2, 1} x threads {256, 512} on a 32-job serving
+            // mix (quarter tables and full tables at 256 threads never won)
+            BatchPlan bestp = {4096, 2, 256};
             for (int tile : {1024, 4096}) {
-                for (int f : {1, 2, 4}) {
-                    alto_status st = launch_group(g, hs, modes, ranks, factors, outs, tile, f, s, dev);
+                for (const std::array<int, 2> ft : {std::array<int, 2>{2, 256}, std::array<int, 2>{2, 512},
+                                                    std::array<int, 2>{4, 512}}) {
+                    const int f = ft[0], th = ft[1];
+                    const BatchPlan bp = {tile, f, th};
+                    alto_status st = launch_group(g, hs, modes, ranks, factors, outs, bp, s, dev);
+                    if (st == ALTO_ERR_ARG && th > 256) continue;  // LDS of the larger block does not fit
                     if (st != ALTO_OK) return st;
                     ALTO_HIP(hipEventRecord(e0, s));
-                    st = launch_group(g, hs, modes, ranks, factors, outs, tile, f, s, dev);
+                    st = launch_group(g, hs, modes, ranks, factors, outs, bp, s, dev);
                     if (st != ALTO_OK) return st;
                     ALTO_HIP(hipEventRecord(e1, s));
                     ALTO_HIP(hipEventSynchronize(e1));
@@ -173,7 +187,7 @@ alto_status group_items(int count, const alto_handle *hs, const int *modes, cons
                     ALTO_HIP(hipEventElapsedTime(&ms, e0, e1));
                     if (ms < best) {
                         best = ms;
-                        bestp = {tile, f};
+                        bestp = bp;
                     }
                 }
             }
@@ -194,11 +208,11 @@ alto_status batched_run(int count, const alto_handle *hs, const int *modes, cons
                         const void *const *const *factors, float *const *outs, hipStream_t s) {
     int dev = 0;
     ALTO_HIP(hipGetDevice(&dev));
-    std::vector<std::pair<Group, std::pair<int, int>>> groups;
+    std::vector<std::pair<Group, BatchPlan>> groups;
     alto_status st = group_items(count, hs, modes, ranks, fdts, factors, outs, s, dev, &groups);
     if (st != ALTO_OK) return st;
     for (const auto &gt : groups) {
-        st = launch_group(gt.first, hs, modes, ranks, factors, outs, gt.second.first, gt.second.second, s, dev);
+        st = launch_group(gt.first, hs, modes, ranks, factors, outs, gt.second, s, dev);
         if (st != ALTO_OK) return st;
     }
     return ALTO_OK;
@@ -209,12 +223,12 @@ alto_status batched_plan(int count, const alto_handle *hs, const int *modes, con
                          std::vector<GroupLaunch> *out) {
     int dev = 0;
     ALTO_HIP(hipGetDevice(&dev));
-    std::vector<std::pair<Group, std::pair<int, int>>> groups;
+    std::vector<std::pair<Group, BatchPlan>> groups;
     alto_status st = group_items(count, hs, modes, ranks, fdts, factors, outs, s, dev, &groups);
     if (st != ALTO_OK) return st;
     for (const auto &gt : groups) {
         GroupLaunch gl;
-        st = plan_group(gt.first, hs, modes, ranks, factors, outs, gt.second.first, gt.second.second, s, dev, &gl);
+        st = plan_group(gt.first, hs, modes, ranks, factors, outs, gt.second, s, dev, &gl);
         if (st != ALTO_OK) return st;
         out->push_back(std::move(gl));
     }
@@ -236,7 +250,7 @@ alto_status launch_planned_group(const GroupLaunch &gl, const void *dblob, hipSt
     void *args[] = {(void *)&djobs, (void *)&dprefix, (void *)&nj, (void *)&xcd_map};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = timing_begin(s, &e0, &e1);
-    ALTO_HIP(hipLaunchKernel(gl.kern, dim3(gl.grid), dim3(256), args, gl.lds, s));
+    ALTO_HIP(hipLaunchKernel(gl.kern, dim3(gl.grid), dim3(gl.threads), args, gl.lds, s));
     if (timed) timing_end(s, e0, e1);
     return ALTO_OK;
 }

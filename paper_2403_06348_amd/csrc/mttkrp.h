@@ -117,7 +117,7 @@ struct GroupLaunch {
     const void *kern = nullptr;
     size_t lds = 0;
     unsigned grid = 1;
-    int nj = 0, xcd_map = 0;
+    int nj = 0, xcd_map = 0, threads = 256;
     size_t jobs_bytes() const { return sizeof(MttkrpArgs) * (size_t)nj; }
     size_t prefix_bytes() const { return 8 * (size_t)(nj + 1); }
     size_t blob_bytes() const { return jobs_bytes() + 2 * prefix_bytes(); }

@@ -1140,7 +1140,7 @@ __global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
 // list (prefix[j] = first tile of job j); each workgroup drains a balanced
 // stretch of it, crossing job boundaries.
 template <int LPN, typename FT, int WORDS, int MAXO>
-__global__ __launch_bounds__(256, 2) void k_mttkrp_batch(const MttkrpArgs *__restrict__ jobs,
+__global__ __launch_bounds__(512) void k_mttkrp_batch(const MttkrpArgs *__restrict__ jobs,
                                                       const uint64_t *__restrict__ prefix, int njobs, int xcd_map) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ uint32_t nkeep;
