@@ -148,50 +148,61 @@ alto_mttkrp_plan default_plan(const alto_tensor *h, int mode, int rank, int fdt)
     // average number of nonzeros per output fiber exceeds the 4 memory
     // operations a buffered update costs in the worst case
     p.conflict = reuse > 4.0 ? ALTO_CR_TILE : ALTO_CR_RUN;
-    p.block_threads = 256;
+    // The defaults follow the autotuner's choices on 34 modes of eight
+    // 0.9e7-2e7-nonzero Zipf tensors of 3-5 modes (R 8-32), where the former
+    // defaults (256 threads, tiles growing to nnz/8192, FP32-row whole-mode
+    // tables) ran 1.2-2x slower on most modes and up to 20x on short skewed
+    // ones: 512 threads in 31 of 34 modes, tiles longer at lower rank.
+    p.block_threads = 512;
     // LDS table of about 64 KiB of FP64 partial rows
     int slots = 8192 / rank;
     int s2 = 1;
     while (s2 * 2 <= slots) s2 *= 2;
     p.table_slots = std::max(64, s2);
-    // long tiles amortize the table flush; keep enough tiles to fill the GPU
+    // long tiles amortize the table flush (the longer the lower the rank);
+    // keep about 2048 tiles to fill the GPU
+    const int tmax = std::min(16384, std::max(2048, pow2_floor(std::max(1, 131072 / rank))));
     uint64_t tile = 512;
-    while (tile < 16384 && tile * 8192 < h->info.nnz) tile *= 2;
+    while (tile < (uint64_t)tmax && tile * 2048 < h->info.nnz) tile *= 2;
     p.tile_nnz = (int)tile;
     p.accumulate = ALTO_ACC_F32;
-    // a mode short enough to hold whole in LDS (with a rank tile of at least
-    // 8 columns) is accumulated there for the workgroup's whole segment: in
-    // FP64 rows if at most two passes (rank tiles) do, else in FP32 rows
-    // (twice the columns per pass, slower adds)
-    const size_t lim = direct_table_limit(h, 512);
+    // a mode short enough to hold whole in LDS in FP64 rows, in at most two
+    // passes (rank tiles of at least 8 columns), is accumulated there for
+    // the workgroup's whole segment.  FP32 rows (added by compare-and-swap)
+    // are left to the autotuner: on skewed modes the swaps of hot rows retry
+    // (5.0 and 9.4 ms against 0.8 and 0.5 ms for the table merge on two
+    // such modes), on uniform ones they can win.
+    const size_t lim = direct_table_limit(h, p.block_threads);
     int rt_d = 0;
-    size_t bytes_d = 0;
-    for (int eb : {8, 4}) {
-        for (int rt = rank; rt >= 8 && rt % 4 == 0 && rank % rt == 0; rt /= 2) {
-            const size_t bytes = (size_t)h->info.dims[mode] * (rt + 1) * eb;
-            if (bytes <= lim) {
-                if (eb == 4 || 2 * rt >= rank) {
-                    rt_d = rt;
-                    bytes_d = bytes;
-                }
-                break;
-            }
+    for (int rt = rank; rt >= 8 && rt % 4 == 0 && rank % rt == 0 && 2 * rt >= rank; rt /= 2) {
+        if ((size_t)h->info.dims[mode] * (rt + 1) * 8 <= lim) {
+            rt_d = rt;
+            break;
         }
-        if (rt_d) break;
     }
     if (rt_d && reuse > 4.0) {
         p.conflict = ALTO_CR_DIRECT;
         p.rank_tile = rt_d == rank ? 0 : rt_d;
-        // one workgroup per CU when the table takes most of the LDS: give it
-        // more waves
-        if (bytes_d > direct_table_limit(h, 256) / 2) p.block_threads = 512;
     }
     (void)fdt;
     return p;
 }
 
+// 32-bit words per whole-mode LDS row element of a plan on this tensor: FP64
+// rows when the rank tile fits so, else FP32 rows (see fill_args).
+int direct_row_words(const alto_tensor *h, int mode, int rank, const alto_mttkrp_plan &p) {
+    const int rt = p.rank_tile > 0 ? p.rank_tile : rank;
+    return (size_t)h->info.dims[mode] * (rt + 1) * 8 <= direct_table_limit(h, p.block_threads) ? 2 : 1;
+}
+
+// Tuned plans per tensor class, with the whole-mode row width the plan had
+// where it was tuned.
+struct CachedPlan {
+    alto_mttkrp_plan p;
+    int row_words;
+};
 static std::mutex g_tune_mu;
-static std::map<std::array<int, 6>, alto_mttkrp_plan> g_tune_cache;
+static std::map<std::array<int, 6>, CachedPlan> g_tune_cache;
 
 std::array<int, 6> tune_key(const alto_tensor *h, int mode, int rank, int fdt) {
     const double reuse = (double)h->info.nnz / (double)h->info.dims[mode];
@@ -203,25 +214,32 @@ std::array<int, 6> tune_key(const alto_tensor *h, int mode, int rank, int fdt) {
 void record_tuned(alto_tensor *h, int mode, int rank, int fdt, const alto_mttkrp_plan &p) {
     h->tuned[mode][fdt][rank / 4] = p;
     h->has_tuned[mode][fdt][rank / 4] = true;
+    const int rw = p.conflict == ALTO_CR_DIRECT ? direct_row_words(h, mode, rank, p) : 0;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[tune_key(h, mode, rank, fdt)] = p;
+    g_tune_cache[tune_key(h, mode, rank, fdt)] = {p, rw};
 }
 
-bool cached_tuned(const alto_tensor *h, int mode, int rank, int fdt, alto_mttkrp_plan *p) {
+bool cached_tuned(const alto_tensor *h, int mode, int rank, int fdt, alto_mttkrp_plan *p, int *row_words) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(tune_key(h, mode, rank, fdt));
     if (it == g_tune_cache.end()) return false;
-    *p = it->second;
+    *p = it->second.p;
+    *row_words = it->second.row_words;
     return true;
 }
 
-// Whether a plan's LDS tables fit this tensor's mode and device.
-bool plan_fits(const alto_tensor *h, int mode, int rank, const alto_mttkrp_plan &p) {
+// Whether a cached plan's LDS tables fit this tensor's mode and device.  A
+// whole-mode plan must also keep the row width it was tuned with: on a
+// longer mode FP64 rows can turn into FP32 rows added by compare-and-swap,
+// which retry on skewed modes (3.4 ms against 0.9 ms for the table merge on
+// a 1338-row mode given the plan tuned on a 1044-row mode of its class).
+bool plan_fits(const alto_tensor *h, int mode, int rank, const alto_mttkrp_plan &p, int row_words) {
     const int rt = p.rank_tile > 0 ? p.rank_tile : rank;
     if (p.block_threads != 256 && p.block_threads != 512) return false;
     if (p.rank_tile < 0 || p.rank_tile % 4 || rank % rt) return false;
     if (p.conflict == ALTO_CR_DIRECT)
-        return (size_t)h->info.dims[mode] * (rt + 1) * 4 <= direct_table_limit(h, p.block_threads);
+        return (size_t)h->info.dims[mode] * (rt + 1) * 4 <= direct_table_limit(h, p.block_threads) &&
+               direct_row_words(h, mode, rank, p) == row_words;
     if (p.conflict == ALTO_CR_TILE || p.conflict == ALTO_CR_HOT)
         return p.table_slots >= 16 && tile_plan_fits(h, rt, p.table_slots, p.block_threads);
     return true;
@@ -283,7 +301,8 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
         // a plan tuned on another tensor of the class is used only where it
         // fits this one (its mode may be longer than the tuned one's)
         alto_mttkrp_plan c;
-        if (cached_tuned(h, mode, rank, fdt, &c) && plan_fits(h, mode, rank, c)) p = c;
+        int rw = 0;
+        if (cached_tuned(h, mode, rank, fdt, &c, &rw) && plan_fits(h, mode, rank, c, rw)) p = c;
     }
     if (in) {
         if (in->conflict) {
