@@ -41,6 +41,11 @@ alto_status plan_group(const Group &g, const alto_handle *hs, const int *modes, 
     gl->prefix.assign(nj + 1, 0);
     gl->oprefix.assign(nj + 1, 0);
     size_t lds = 0;
+    // one tile length for every job of the launch (at least each job's
+    // nnz / kBatchF32MaxTiles), so that equal tile counts are equal work
+    uint64_t tlen = (uint64_t)tile;
+    for (int k = 0; k < nj; k++)
+        tlen = std::max<uint64_t>(tlen, (hs[g.items[k]]->info.nnz + kBatchF32MaxTiles - 1) / kBatchF32MaxTiles);
     for (int k = 0; k < nj; k++) {
         const int j = g.items[k];
         alto_tensor *h = hs[j];
@@ -51,7 +56,7 @@ alto_status plan_group(const Group &g, const alto_handle *hs, const int *modes, 
         p.accumulate = ALTO_ACC_F32;
         // FP32 atomics into the output: a row takes at most one addition per
         // tile, so long tensors get longer tiles (see accuracy_policy)
-        p.tile_nnz = (int)std::max<uint64_t>((uint64_t)tile, (h->info.nnz + kBatchF32MaxTiles - 1) / kBatchF32MaxTiles);
+        p.tile_nnz = (int)tlen;
         // table rows: slots_factor quarters of the single-tensor default
         p.table_slots = std::max(16, p.table_slots * slots_factor / 4);
         // one LDS size serves the whole launch: keep every table within
