@@ -138,6 +138,31 @@ def test_batched_sweep_mixed_factor_types_match_oracle():
         T.free()
 
 
+def test_batched_sweep_with_a_job_that_runs_alone_matches_oracle():
+    """A batched sweep mixing small tensors (shared batched launches) with one
+    of 1.2e6 nonzeros, above the 2^20 threshold at which a tensor takes its
+    own MTTKRP launches with its mode's plan: every mode of every item
+    against the oracle's update from the factors that mode saw."""
+    specs = [((3000, 2000, 500), 20_000, (1.2, 1.2, 1.2), 16, 51),
+             ((200_000, 150_000, 3_000), 1_200_000, (1.2, 1.2, 1.2), 16, 52),
+             ((5000, 300, 20, 4000), 60_000, (1.2, None, None, 1.2), 8, 53)]
+    jobs, items = [], []
+    for dims, nnz, ex, R, seed in specs:
+        X = zipf_tensor(dims, nnz, ex, seed=seed)
+        T = alto.AltoTensor(X.dims, torch.from_numpy(X.coords).cuda(), torch.from_numpy(vals32(X)).cuda())
+        f0 = [torch.from_numpy(f).cuda() for f in make_factors(X.dims, R, seed=seed + 1)]
+        jobs.append((X, T, f0))
+        items.append((T, [f.clone() for f in f0], torch.empty(R, dtype=torch.float64, device="cuda"), alto.F32))
+    say(f"[batched] sweep with a 1.2e6-nonzero item among {len(items)}")
+    alto.sweep_batched(items)
+    torch.cuda.synchronize()
+    for k, (it, (X, _, f0)) in enumerate(zip(items, jobs)):
+        check_sweep(X.dims, X.coords, vals32(X), [f.cpu().numpy() for f in f0],
+                    [f.cpu().numpy() for f in it[1]], it[2].cpu().numpy(), what=f"item {k} (nnz {X.nnz})")
+    for _, T, _ in jobs:
+        T.free()
+
+
 def test_prepared_batch_graph_replays_match_oracle():
     """A prepared batched sweep (alto_sweep_batch_*) captured in one HIP
     graph.  Its eager run and every replay -- with eager work and
