@@ -336,16 +336,22 @@ alto_status autotune_run(alto_tensor *h, int mode, int rank, int fdt, const void
             }
         }
     }
-    // the whole mode in LDS, for short modes
+    // the whole mode in LDS, for short modes (the tile length sets only the
+    // stretch granularity there: the default's and a long one)
     for (int rt = rank; rt >= 4; rt /= 2) {
         if (rt % 4 || rank % rt) break;
         for (int threads : {256, 512}) {
             if ((size_t)h->info.dims[mode] * (rt + 1) * 4 > direct_table_limit(h, threads)) continue;
-            alto_mttkrp_plan p = base;
-            p.conflict = ALTO_CR_DIRECT;
-            p.rank_tile = rt == rank ? 0 : rt;
-            p.block_threads = threads;
-            cands.push_back(p);
+            for (int tile : {base.tile_nnz, 16384}) {
+                if (tile == 16384 && base.tile_nnz == 16384) continue;
+                if (nnz > 0 && (uint64_t)tile * 64 > nnz && tile != base.tile_nnz) continue;
+                alto_mttkrp_plan p = base;
+                p.conflict = ALTO_CR_DIRECT;
+                p.rank_tile = rt == rank ? 0 : rt;
+                p.block_threads = threads;
+                p.tile_nnz = tile;
+                cands.push_back(p);
+            }
         }
     }
     const double reuse = nnz / (double)h->info.dims[mode];
