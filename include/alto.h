@@ -108,6 +108,22 @@ typedef enum {
     ALTO_ACC_XCD_F64 = 4
 } alto_accumulate;
 
+/* Order in which the workgroups of a launch take the tiles (Sec. "Workload
+ * Partitioning and Scheduling": nnz-balanced line segments per worker).
+ * The tiles are split into one contiguous range per XCD either way.
+ * ALTO_ORDER_CONTIGUOUS: each workgroup takes a contiguous stretch of its
+ *   XCD's range (rows that recur in neighbouring tiles stay in its LDS table).
+ * ALTO_ORDER_INTERLEAVED: the XCD's workgroups take its tiles round-robin, so
+ *   the tiles in flight on one XCD are neighbours on the line and share L2
+ *   lines of factor and output rows (TILE, RUN and DIRECT plans; HOT plans
+ *   always use stretches).
+ * ALTO_ORDER_DEFAULT (0): contiguous unless the autotuner recorded otherwise. */
+typedef enum {
+    ALTO_ORDER_DEFAULT = 0,
+    ALTO_ORDER_CONTIGUOUS = 1,
+    ALTO_ORDER_INTERLEAVED = 2
+} alto_tile_order;
+
 /* Tunable launch plan of one MTTKRP.  Zero fields take the library default
  * (or the autotuned value when one was recorded for the handle and mode). */
 typedef struct {
@@ -117,6 +133,7 @@ typedef struct {
     int table_slots;     /* LDS merge-table rows (power of two), TILE and HOT      */
     int accumulate;      /* alto_accumulate                                        */
     int rank_tile;       /* columns per pass (multiple of 4 dividing rank; 0: all) */
+    int tile_order;      /* alto_tile_order: which tiles a workgroup takes          */
 } alto_mttkrp_plan;
 
 /* Host-side description of a handle (see alto_info). */

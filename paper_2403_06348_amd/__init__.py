@@ -14,12 +14,14 @@ import ctypes
 from . import _capi
 from ._capi import (  # noqa: F401
     ACC_DEFAULT, ACC_F32, ACC_F64, ACC_XCD_F32, ACC_XCD_F64, BF16, CR_AUTO, CR_DIRECT, CR_HOT, CR_RUN, CR_TILE, F32, MttkrpPlan, STATUS_NAMES,
+    ORDER_CONTIGUOUS, ORDER_DEFAULT, ORDER_INTERLEAVED,
 )
 
 __all__ = [
     "AltoError", "AltoTensor", "plan_dims", "plan_decode_host", "mttkrp_batched", "sweep_batched", "SweepBatch",
     "version", "F32", "BF16",
     "CR_AUTO", "CR_TILE", "CR_RUN", "CR_DIRECT", "CR_HOT", "ACC_DEFAULT", "ACC_F64", "ACC_F32", "ACC_XCD_F32", "ACC_XCD_F64",
+    "ORDER_DEFAULT", "ORDER_CONTIGUOUS", "ORDER_INTERLEAVED",
 ]
 
 

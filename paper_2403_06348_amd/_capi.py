@@ -41,6 +41,10 @@ ACC_F32 = 2
 ACC_XCD_F32 = 3
 ACC_XCD_F64 = 4
 
+ORDER_DEFAULT = 0
+ORDER_CONTIGUOUS = 1
+ORDER_INTERLEAVED = 2
+
 
 class MttkrpPlan(ctypes.Structure):
     _fields_ = [
@@ -50,6 +54,7 @@ class MttkrpPlan(ctypes.Structure):
         ("table_slots", ctypes.c_int),
         ("accumulate", ctypes.c_int),
         ("rank_tile", ctypes.c_int),
+        ("tile_order", ctypes.c_int),
     ]
 
     def as_dict(self):

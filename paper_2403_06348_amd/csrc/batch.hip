@@ -360,11 +360,6 @@ alto_status autotune_run(alto_tensor *h, int mode, int rank, int fdt, const void
         p.conflict = ALTO_CR_RUN;
         cands.push_back(p);
     }
-    hipEvent_t e0, e1;
-    ALTO_HIP(hipEventCreate(&e0));
-    ALTO_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
-    alto_mttkrp_plan bestp = base;
     for (auto &p : cands) accuracy_policy(h, mode, rank, &p);
     // plans the policy moved to FP64: time the other FP64 form too
     const size_t nbase = cands.size();
@@ -372,26 +367,57 @@ alto_status autotune_run(alto_tensor *h, int mode, int rank, int fdt, const void
         alto_mttkrp_plan p = cands[i];
         if (alternate_f64(h, mode, rank, &p)) cands.push_back(p);
     }
-    for (const auto &p : cands) {
-        st = run_mttkrp(h, mode, rank, fdt, factors, out, p, s);  // warm
-        if (st != ALTO_OK) break;
+    hipEvent_t e0, e1;
+    ALTO_HIP(hipEventCreate(&e0));
+    ALTO_HIP(hipEventCreate(&e1));
+    // one warm launch, then two timed ones
+    auto time_plan = [&](const alto_mttkrp_plan &p, float *ms) -> alto_status {
+        alto_status r = run_mttkrp(h, mode, rank, fdt, factors, out, p, s);
+        if (r != ALTO_OK) return r;
         ALTO_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < 2; r++) {
-            st = run_mttkrp(h, mode, rank, fdt, factors, out, p, s);
-            if (st != ALTO_OK) break;
+        for (int k = 0; k < 2; k++) {
+            r = run_mttkrp(h, mode, rank, fdt, factors, out, p, s);
+            if (r != ALTO_OK) return r;
         }
         ALTO_HIP(hipEventRecord(e1, s));
         ALTO_HIP(hipEventSynchronize(e1));
+        ALTO_HIP(hipEventElapsedTime(ms, e0, e1));
+        return ALTO_OK;
+    };
+    std::vector<std::pair<float, alto_mttkrp_plan>> timed;
+    for (const auto &p : cands) {
         float ms = 0.f;
-        ALTO_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            bestp = p;
+        st = time_plan(p, &ms);
+        if (st != ALTO_OK) break;
+        timed.push_back({ms, p});
+    }
+    // the three fastest again with their tiles dealt round-robin within each
+    // XCD (tile order is a property of the launch, independent of the rest)
+    if (st == ALTO_OK) {
+        std::stable_sort(timed.begin(), timed.end(),
+                         [](const std::pair<float, alto_mttkrp_plan> &x, const std::pair<float, alto_mttkrp_plan> &y) {
+                             return x.first < y.first;
+                         });
+        const size_t top = std::min<size_t>(3, timed.size());
+        for (size_t i = 0; i < top && st == ALTO_OK; i++) {
+            alto_mttkrp_plan p = timed[i].second;
+            if (p.conflict == ALTO_CR_HOT) continue;
+            p.tile_order = ALTO_ORDER_INTERLEAVED;
+            float ms = 0.f;
+            st = time_plan(p, &ms);
+            if (st == ALTO_OK) timed.push_back({ms, p});
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != ALTO_OK) return st;
+    alto_mttkrp_plan bestp = base;
+    float best = 1e30f;
+    for (const auto &tp : timed)
+        if (tp.first < best) {
+            best = tp.first;
+            bestp = tp.second;
+        }
     record_tuned(h, mode, rank, fdt, bestp);
     st = run_mttkrp(h, mode, rank, fdt, factors, out, bestp, s);
     if (st != ALTO_OK) return st;

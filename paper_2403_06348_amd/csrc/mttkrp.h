@@ -41,6 +41,7 @@ struct MttkrpArgs {
     uint32_t col0;    // first column of this rank tile
     uint64_t copy_stride;  // elements per copy
     int lut;               // 1: 3 modes, one index word, <= 21 bits per mode (nibble-table decode)
+    int interleave;        // 1: an XCD's workgroups take its tiles round-robin (with xcd_map)
     // CP-APR Phi forms: B (dims[mode] x ld FP32), Pi (nnz x ld FP32, ALTO
     // order; ALTO-PRE only), the divisor floor eps
     const float *phi_B;

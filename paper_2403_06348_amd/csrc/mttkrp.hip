@@ -310,6 +310,7 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
             p.rank_tile = 0;
         }
         if (in->rank_tile) p.rank_tile = in->rank_tile;
+        if (in->tile_order) p.tile_order = in->tile_order;
         if (in->tile_nnz) p.tile_nnz = in->tile_nnz;
         if (in->block_threads) p.block_threads = in->block_threads;
         if (in->table_slots) p.table_slots = in->table_slots;
@@ -323,6 +324,8 @@ alto_status resolve_plan(const alto_tensor *h, int mode, int rank, int fdt, cons
         return fail(ALTO_ERR_ARG, "bad conflict mode");
     if (p.conflict == ALTO_CR_HOT && h->info.nmodes > 5)
         return fail(ALTO_ERR_ARG, "hot-row merging supports tensors of up to 5 modes");
+    if (p.tile_order < ALTO_ORDER_DEFAULT || p.tile_order > ALTO_ORDER_INTERLEAVED)
+        return fail(ALTO_ERR_ARG, "bad tile order");
     if (p.rank_tile < 0 || p.rank_tile % 4 || (p.rank_tile > 0 && rank % p.rank_tile))
         return fail(ALTO_ERR_ARG, "rank_tile must be a multiple of 4 dividing rank");
     const int rt = p.rank_tile > 0 ? p.rank_tile : rank;
@@ -460,6 +463,7 @@ void fill_args(const alto_tensor *h, int mode, int rank, int fdt, const void *co
     while ((1 << l2) < p.table_slots) l2++;
     a->slots_log2 = l2;
     a->rec = record_words(h->info.nmodes, h->info.index_words);
+    a->interleave = p.tile_order == ALTO_ORDER_INTERLEAVED && p.conflict != ALTO_CR_HOT;
     a->lut = h->info.nmodes == 3 && h->info.index_words == 1;
     for (int m = 0; m < h->info.nmodes; m++)
         if (h->info.nbits[m] > 21) a->lut = 0;

@@ -354,21 +354,22 @@ __device__ inline uint32_t rec_coord(const uint4 &h, const uint4 &h2, int k) {
     return k == 0 ? h.z : k == 1 ? h.w : k == 2 ? h2.x : k == 3 ? h2.y : k == 4 ? h2.z : h2.w;
 }
 
-// End of tile t of the stretch [t0, t1): the LDS table's rows go to the
-// output -- for a whole-mode table (TM 2) once, at the stretch's end; for a
-// hashed table (TM 1) every tile, except rows merged many times (high
-// reuse), which stay for the next tile.  Everything is flushed every
-// kKeepTiles tiles and at the end of the stretch.
+// End of a tile of the workgroup's tiles (`last`: its final one; `ord`: how
+// many it processed before this one): the LDS table's rows go to the output
+// -- for a whole-mode table (TM 2) once, after the final tile; for a hashed
+// table (TM 1) every tile, except rows merged many times (high reuse), which
+// stay for the next tile.  Everything is flushed every kKeepTiles tiles and
+// after the final one.
 template <int FA>
 __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int TS, uint32_t *tkey, uint32_t *thits,
-                                void *tval, uint32_t &nkeep, uint64_t t, uint64_t t0, uint64_t t1) {
+                                void *tval, uint32_t &nkeep, bool last, uint64_t ord) {
     const int tid = threadIdx.x;
     double *tv64 = (double *)tval;
     float *tv32 = (float *)tval;
     // one column per thread (see global_add1); sh: log2(rank), or -1
     const int rk = a.rank;
     const int sh = (rk & (rk - 1)) == 0 ? __ffs(rk) - 1 : -1;
-    if (TM == 2 && t + 1 == t1) {
+    if (TM == 2 && last) {
         // ---- end of the stretch: every row of the mode held in LDS is
         // added to the output once
         __syncthreads();
@@ -384,7 +385,7 @@ __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int 
             }
         }
         __syncthreads();
-    } else if (TM == 3 && t + 1 == t1) {
+    } else if (TM == 3 && last) {
         // ---- end of the stretch: the hot rows' partial sums go to the output
         __syncthreads();
         for (int i = tid; i < S * rk; i += blockDim.x) {
@@ -398,7 +399,7 @@ __device__ inline void tile_end(const MttkrpArgs &a, int TM, int TW, int S, int 
         __syncthreads();
     } else if (TM == 1) {
         __syncthreads();
-        const bool flush_all = (t + 1 == t1) || ((t - t0 + 1) % kKeepTiles == 0);
+        const bool flush_all = last || ((ord + 1) % kKeepTiles == 0);
         if (tid == 0) nkeep = 0;
         __syncthreads();
         for (int i = tid; i < S; i += blockDim.x) {
@@ -652,7 +653,7 @@ __device__ inline void mttkrp_stretch(const MttkrpArgs &a, uint32_t *smem, uint3
         }
         if (cur != kEmptyRow) flush_run<TMC, false>(a, tval, thits, cur, q, r0, acc);
 
-        tile_end<false>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
+        tile_end<false>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t + 1 == t1, t - t0);
     }
 }
 
@@ -863,7 +864,7 @@ constexpr int kOpMttkrp = 0, kOpPhi = 1, kOpPhiPre = 2;
 template <int LPN, typename FT, int WORDS, int MAXO, int TMC, bool FAST, int OP = kOpMttkrp, int FA = 0>
 __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, uint32_t &nkeep,
                                            const uint64_t *lmask, uint64_t t0, uint64_t t1,
-                                           const uint64_t *lut = nullptr) {
+                                           const uint64_t *lut = nullptr, uint64_t tstep = 1) {
     static_assert(MAXO == 2 || MAXO == 4, "pipelined stretch: up to 5 modes");
     static_assert(OP == kOpMttkrp || (MAXO == 4 && !FAST), "Phi forms use 8-word records");
     const int TM = TMC >= 0 ? TMC : a.tile_merge;
@@ -918,7 +919,7 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
         __syncthreads();
     }
 
-    for (uint64_t t = t0; t < t1; t++) {
+    for (uint64_t t = t0; t < t1; t += tstep) {
         const uint64_t ts = t * a.tq + (t * a.tr) / a.ntiles;
         const uint64_t te = (t + 1) * a.tq + ((t + 1) * a.tr) / a.ntiles;
         const uint64_t per = (te - ts + ngrp - 1) / ngrp;
@@ -1100,7 +1101,7 @@ __device__ inline void mttkrp_stretch_pipe(const MttkrpArgs &a, uint32_t *smem, 
         }
         ob_drain<FA>(ob, a, obn);
         __builtin_amdgcn_wave_barrier();
-        tile_end<FA>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t, t0, t1);
+        tile_end<FA>(a, TM, TW, S, TS, tkey, thits, tval, nkeep, t + tstep >= t1, (t - t0) / tstep);
     }
 }
 
@@ -1127,10 +1128,19 @@ __global__ __launch_bounds__(512) void k_mttkrp(const MttkrpArgs a) {
     // the pipelined loop (with the per-wave outboxes) for up to 5 modes; the
     // plain loop for 6-8 modes
     if constexpr (FAST || MAXO <= 4) {
+        uint64_t tstep = 1;
+        if (a.xcd_map && a.interleave) {
+            // the XCD's tiles (the same contiguous range as above) dealt
+            // round-robin to its G/8 workgroups (G is a multiple of 8 here)
+            const uint32_t g8 = gridDim.x / 8, x = blockIdx.x % 8;
+            t0 = (a.ntiles * x) / 8 + blockIdx.x / 8;
+            t1 = (a.ntiles * (x + 1)) / 8;
+            tstep = g8;
+        }
         load_masks(a.lp, a.nmodes, lmask);
         if (kUseLut<FAST, WORDS, LPN> && a.lut) build_nibble_lut(lmask, lut);
         mttkrp_stretch_pipe<LPN, FT, WORDS, MAXO, TMC, FAST, kOpMttkrp, FAST ? (F64 ? 2 : 1) : 0>(a, smem, nkeep, lmask,
-                                                                                              t0, t1, lut);
+                                                                                              t0, t1, lut, tstep);
     } else {
         mttkrp_stretch<LPN, FT, WORDS, MAXO, TMC>(a, smem, nkeep, t0, t1);
     }

@@ -128,6 +128,8 @@ def test_mttkrp_argument_errors():
         T.mttkrp(0, [gf[0], None, gf[2]])
     with pytest.raises(alto.AltoError):
         T.mttkrp(0, gf, plan=dict(table_slots=100, conflict=alto.CR_TILE))
+    with pytest.raises(alto.AltoError):
+        T.mttkrp(0, gf, plan=dict(tile_order=3))
 
 
 def test_autotune_records_a_plan_and_stays_exact():
@@ -236,6 +238,34 @@ def test_mttkrp_whole_mode_lds_and_rank_tiles(name, rank, mode, plan):
     say(f"[mttkrp] {name} R={rank} mode={mode} plan={plan}")
     got = T.mttkrp(mode, gf, plan=plan).cpu().numpy().astype(np.float64)
     check(got, ref, X, facs, mode, f"{name} R={rank} mode {mode} {plan}")
+
+
+@pytest.mark.parametrize("name,rank,mode,plan", [
+    # hashed tables with retention across a workgroup's tiles, FP32 and FP64 sums
+    ("c2s", 16, 0, dict(conflict=alto.CR_TILE, tile_nnz=512)),
+    ("c2s", 16, 2, dict(conflict=alto.CR_TILE, tile_nnz=512, accumulate=alto.ACC_F64)),
+    ("c2s", 16, 2, dict(conflict=alto.CR_TILE, tile_nnz=1024, accumulate=alto.ACC_XCD_F64, block_threads=512)),
+    # whole-mode tables (flushed once, after a workgroup's last tile)
+    ("c3s", 32, 2, dict(conflict=alto.CR_DIRECT, rank_tile=16, tile_nnz=512)),
+    ("c3s", 32, 1, dict(conflict=alto.CR_DIRECT, rank_tile=16, block_threads=512, tile_nnz=512)),
+    # register runs, a 4-mode general kernel, rank tiles
+    ("c2s", 16, 1, dict(conflict=alto.CR_RUN, tile_nnz=512)),
+    ("c3s", 32, 0, dict(conflict=alto.CR_TILE, tile_nnz=512, rank_tile=16)),
+])
+def test_mttkrp_interleaved_tile_order(name, rank, mode, plan):
+    """Tiles dealt round-robin to the workgroups of each XCD (short tiles, so
+    that there are several per workgroup): every entry against the oracle,
+    and against the same plan with contiguous stretches."""
+    X, T = built(name)
+    facs = factors_for(X, rank, seed=rank + 3)
+    ref = oracle_modes(X, facs)[mode]
+    gf = [torch.from_numpy(f).cuda() for f in facs]
+    say(f"[mttkrp] interleaved {name} R={rank} mode={mode} plan={plan}")
+    got = T.mttkrp(mode, gf, plan=dict(plan, tile_order=alto.ORDER_INTERLEAVED)).cpu().numpy().astype(np.float64)
+    check(got, ref, X, facs, mode, f"interleaved {name} R={rank} mode {mode} {plan}")
+    cont = T.mttkrp(mode, gf, plan=dict(plan, tile_order=alto.ORDER_CONTIGUOUS)).cpu().numpy().astype(np.float64)
+    check(cont, ref, X, facs, mode, f"contiguous {name} R={rank} mode {mode} {plan}")
+    assert rel_fro(got, cont) <= 2e-6
 
 
 def test_plans_beyond_the_lds_are_rejected():
