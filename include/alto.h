@@ -346,9 +346,12 @@ alto_status cpd_als_sweep_ex(alto_handle h, int rank, alto_dtype fdt, float *con
 
 /*
  * One CP-ALS sweep of each of `count` tensors at once: for every mode step n,
- * the MTTKRPs of all tensors that have a mode n run in one persistent
- * launch per kernel variant (as alto_mttkrp_batched), around each tensor's
- * own FP64 R x R solve and normalisation.  Per item as cpd_als_sweep_ex:
+ * the MTTKRPs of the tensors below 2^20 nonzeros that have a mode n run in
+ * one persistent launch per kernel variant (as alto_mttkrp_batched), and
+ * each larger tensor's in a launch of its own with its mode's plan (FP32
+ * atomics or one FP64 buffer, never per-XCD copies); the FP64 Grams, R x R
+ * solves and normalisations of all tensors run as one launch per step.  Per
+ * item as cpd_als_sweep_ex:
  * hs[j], ranks[j], fdts[j], factors[j] (host array of device pointers),
  * lambdas[j] (device [ranks[j]]).  Tensors may differ in order, dims and
  * rank.  Results equal separate sweeps up to FP32 summation order.
