@@ -480,8 +480,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding of the MTTKRP is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
