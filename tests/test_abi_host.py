@@ -54,3 +54,41 @@ def test_plan_argument_errors(dims, status):
     with pytest.raises(alto.AltoError) as e:
         alto.plan_dims(dims)
     assert e.value.status == status
+
+
+def _header_structs():
+    """Field names, in order, of every `typedef struct { ... } name;` in
+    include/alto.h (array fields by name, comma lists expanded)."""
+    import os
+    import re
+
+    path = os.path.join(os.path.dirname(_capi.LIB_PATH), os.pardir, "include", "alto.h")
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(\w+)\s*;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            # type then one or more declarators: "uint64_t a, b[4]"
+            m = re.match(r"^(?:const\s+)?[\w\s\*]+?\s+(\**\w+(?:\[[^\]]*\])?(?:\s*,\s*\**\w+(?:\[[^\]]*\])?)*)$", decl)
+            assert m, (name, decl)
+            for d in m.group(1).split(","):
+                fields.append(re.sub(r"[\*\s]|\[.*\]", "", d))
+        out[name] = fields
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [
+    ("alto_mttkrp_plan", "MttkrpPlan"), ("alto_info_t", "Info"), ("alto_cpapr_params", "CpaprParams"),
+    ("alto_serve_job", "ServeJob"), ("alto_serve_stats", "ServeStats"), ("alto_serve_done", "ServeDone"),
+])
+def test_binding_structs_match_header(cname, pyname):
+    """Every struct the binding passes across the ABI has the header's fields
+    in the header's order (a field added on one side only would shift the
+    rest)."""
+    hdr = _header_structs()[cname]
+    py = [f for f, _ in getattr(_capi, pyname)._fields_]
+    assert py == hdr, (cname, hdr, py)
